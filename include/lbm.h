@@ -1,0 +1,183 @@
+/*
+ * lbm.h - C ABI of the MI355X library for the phase-field lattice Boltzmann
+ * method for insoluble surfactant transport in two-phase flows
+ * (Zhan, Liang, Chai, Shi, arXiv:2408.15654).
+ *
+ * One simulation ("handle") advances three coupled D2Q9 lattice Boltzmann
+ * fields on one GPU:
+ *   f  conservative Allen-Cahn phase field phi       Sec. 3.1, Eqs. (21)-(24)
+ *   g  interface-confined surfactant psi             Sec. 3.2, Eqs. (25)-(28)
+ *   h  consistent Navier-Stokes (u, P)               Sec. 3.3, Eqs. (29)-(33)
+ * with the capillary and Marangoni force of Eq. (18), the mass flux of
+ * Eq. (16) and the equations of state (19)/(20).  All lattice quantities are
+ * in lattice units (dx = dt = 1, c_s^2 = 1/3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout   Host fields are float64 arrays of nx*ny values, row-major with x
+ *          fastest: site (x, y) is element y*nx + x.
+ * Memory   The caller owns the device workspace (size from
+ *          lbm_workspace_bytes) and must keep it alive until lbm_destroy.
+ *          Host arrays are only read or written during the call.
+ * Streams  All device work is enqueued on the HIP stream given to
+ *          lbm_create (NULL = the null stream).  lbm_step does not wait for
+ *          the device; lbm_read_fields, lbm_moments and lbm_get_state
+ *          synchronise the stream.
+ * Errors   Every call returns an lbm_status; no C++ exception crosses the
+ *          ABI.  A call that fails leaves the simulation as it was;
+ *          lbm_last_error gives a message.  A non-finite value produced on
+ *          the device raises a sticky device flag that the next
+ *          synchronising call reports as LBM_ENONFINITE; after that,
+ *          lbm_step returns LBM_ESTATE until lbm_init_fields or
+ *          lbm_set_state.
+ * Threads  A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument or parameter */
+  LBM_ENOMEM = -2,     /* workspace too small */
+  LBM_EDEVICE = -3,    /* HIP runtime error */
+  LBM_ENONFINITE = -4, /* the device produced a NaN or Inf */
+  LBM_ESTATE = -5      /* no valid state (not initialised, or after ENONFINITE) */
+} lbm_status;
+
+/* Storage precision of the populations.  LBM_FP64: float64 storage and
+ * arithmetic.  LBM_FP32: float32 storage and arithmetic.  LBM_FP16DEV: each
+ * population stored as a float16 deviation from its rest equilibrium
+ * (w_i phi for f, w_i psi for g, 0 for h), scaled by a power of two, with
+ * float32 arithmetic. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16DEV = 2 } lbm_precision;
+
+/* Equation of state sigma(psi): linear Eq. (20) or Langmuir Eq. (19). */
+typedef enum { LBM_EOS_LINEAR = 0, LBM_EOS_LANGMUIR = 1 } lbm_eos;
+
+/* Problem parameters, named after the paper's statement of the problem.
+ * Relaxation rates follow from the transport coefficients:
+ *   1/s1^f = M/c_s^2 + 1/2        (Eq. (23), tau_phi = 3M + 1/2)
+ *   1/s1^g = D/c_s^2 + 1/2        (Eq. (28), tau_psi = 3D + 1/2)
+ *   1/s2^h = mu/(rho c_s^2) + 1/2 (Eq. (33), per site, tau_f = 3 mu/rho + 1/2)
+ * The remaining rates of S^k (Eq. (34)) are free and taken from s_free. */
+typedef struct {
+  int32_t nx, ny;       /* lattice sites; nx, ny >= 3; x is periodic        */
+  int32_t walls_y;      /* 0: periodic in y; 1: half-way bounce-back walls
+                           below row 0 and above row ny-1 (Sec. 4)          */
+  int32_t eos;          /* lbm_eos                                          */
+  int32_t precision;    /* lbm_precision                                    */
+  int32_t reserved;     /* must be 0                                        */
+  double u_wall_bot;    /* tangential (x) speed of the bottom wall          */
+  double u_wall_top;    /* tangential (x) speed of the top wall             */
+  double phiA, phiB;    /* order parameter in fluids A and B, phiA > phiB   */
+  double W;             /* interface width, > 0                             */
+  double M;             /* mobility M_phi, > 0                              */
+  double D;             /* surfactant diffusivity, > 0                      */
+  double r;             /* normal-diffusion ratio of Eq. (3), >= 0 (1 is the
+                           paper's LB model, Eq. (26))                      */
+  double rhoA, rhoB;    /* densities, > 0 (Eq. (15))                        */
+  double muA, muB;      /* dynamic viscosities, > 0 (Eq. (15))              */
+  double sigma0;        /* clean-interface surface tension, >= 0            */
+  double beta;          /* elasticity number E_0 of Eqs. (19)-(20)          */
+  double gx, gy;        /* body force per unit mass: F_b = rho (gx, gy)     */
+  double s_free[3][3];  /* free rates: [0] f: s2,s3,s4  [1] g: s2,s3,s4
+                           [2] h: s1,s3,s4; each in (0, 2)                  */
+  double fp16_scale[3]; /* LBM_FP16DEV only: power-of-two scale of the
+                           stored deviations of f, g, h (0 = default)       */
+} lbm_params;
+
+/* Domain-wide sums of the current time level, accumulated in float64. */
+typedef struct {
+  int64_t step;      /* time steps taken since lbm_init_fields           */
+  double sum_phi;    /* sum of phi                                       */
+  double sum_psi;    /* sum of psi (total surfactant)                    */
+  double mom_x;      /* sum of rho ux                                    */
+  double mom_y;      /* sum of rho uy                                    */
+  double kinetic;    /* sum of rho |u|^2 / 2                             */
+  double max_u;      /* max |u|                                          */
+  int32_t nonfinite; /* 1 if any of phi, psi, u is not finite            */
+  int32_t pad;
+} lbm_moments_t;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Bytes of device workspace a simulation with these parameters needs
+ * (populations twice, per-site history, float64 scratch for read-back).
+ * Returns 0 if the parameters are invalid. */
+size_t lbm_workspace_bytes(const lbm_params *params);
+
+/* Validate params and carve the caller's device workspace.
+ * dev_ws: device pointer, 256-byte aligned, ws_bytes >= lbm_workspace_bytes.
+ * hip_stream: a hipStream_t (or NULL).  *out receives the handle.
+ * Errors: LBM_EINVAL (bad parameter, see the struct), LBM_ENOMEM (workspace
+ * too small), LBM_EDEVICE. */
+lbm_status lbm_create(const lbm_params *params, void *dev_ws, size_t ws_bytes,
+                      void *hip_stream, lbm_handle **out);
+
+/* Set the initial state from host float64 fields (nx*ny each): phi, psi,
+ * ux, uy.  Post-collision populations become the equilibria of Eqs. (22),
+ * (26), (30) with P = 0 and S from Eq. (16); the stored previous time level
+ * is these fields, so the first time differences are taken against them.
+ * Computed in float64 on the device, then rounded to the storage precision.
+ * Resets the step counter and the non-finite flag.
+ * Errors: LBM_EINVAL (NULL array, non-finite value, psi >= 1 with the
+ * Langmuir EOS), LBM_EDEVICE. */
+lbm_status lbm_init_fields(lbm_handle *h, const double *phi, const double *psi,
+                           const double *ux, const double *uy);
+
+/* Advance nsteps >= 0 time steps: each is one launch of the fused
+ * stream-collide kernel (pull streaming with half-way bounce-back, the
+ * gradient stencils, forces, closures (32a)-(32b), and the three MRT
+ * collisions of Eqs. (21), (25), (29) in moment space).  Asynchronous.
+ * Errors: LBM_EINVAL (nsteps < 0), LBM_ESTATE, LBM_EDEVICE. */
+lbm_status lbm_step(lbm_handle *h, int64_t nsteps);
+
+/* Macroscopic fields of the current time level (phi, psi by Eqs. (24),
+ * (27); u and P by Eqs. (32a)-(32b)) into host float64 arrays of nx*ny
+ * values.  A NULL pointer skips that field.  Synchronises the stream.
+ * Errors: LBM_ESTATE, LBM_ENONFINITE, LBM_EDEVICE. */
+lbm_status lbm_read_fields(lbm_handle *h, double *phi, double *psi, double *ux,
+                           double *uy, double *P);
+
+/* Float64 domain sums of the current time level (deterministic order).
+ * Synchronises the stream.  Errors: LBM_EINVAL (NULL out), LBM_ESTATE,
+ * LBM_ENONFINITE, LBM_EDEVICE. */
+lbm_status lbm_moments(lbm_handle *h, lbm_moments_t *out);
+
+/* Checkpoint: the raw state (populations, previous level, step counter) in
+ * storage precision.  lbm_state_bytes gives the size; lbm_get_state copies
+ * it to host memory (synchronising), lbm_set_state restores it, after which
+ * stepping continues bit for bit as from the saved point.
+ * Errors: LBM_EINVAL (NULL or size mismatch), LBM_ENONFINITE (get),
+ * LBM_ESTATE (get before init), LBM_EDEVICE. */
+size_t lbm_state_bytes(const lbm_handle *h);
+lbm_status lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes);
+lbm_status lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
+
+/* Release the handle (not the caller's workspace).  NULL is ignored. */
+void lbm_destroy(lbm_handle *h);
+
+/* Message of the last failed call on h (or of the last failed lbm_create
+ * when h is NULL).  Valid until the next call on h. */
+const char *lbm_last_error(const lbm_handle *h);
+
+/* Rows of lattice each wavefront of the step kernel walks through (its tile
+ * height).  0 restores the default.  Errors: LBM_EINVAL (< 0 or > 4096). */
+lbm_status lbm_set_tile_rows(lbm_handle *h, int32_t rows);
+
+/* Name of the device kernel lbm_step launches for this handle (for
+ * profiler look-ups). */
+const char *lbm_step_kernel_name(const lbm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

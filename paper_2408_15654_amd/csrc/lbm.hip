@@ -1,0 +1,930 @@
+// HIP kernels and C ABI of the coupled three-field lattice Boltzmann library
+// (phase field f, surfactant g, flow h; arXiv:2408.15654), for gfx950.
+//
+// State on the device (structure of arrays, x fastest, one plane per
+// population, planes padded to 64 elements):
+//   populations  planes 0-8 f_0..f_8, 9-17 g_0..g_8, 18-25 h_1..h_8 (h_0 is
+//                never read, see lbm_device.h), post-collision values of the
+//                previous step, two copies (ping-pong);
+//   aux          planes phi, psi, ux, uy, Sx, Sy of the previous time level
+//                (the first-order time differences need them), updated in
+//                place: every site reads and writes only its own entries;
+//   scratch      float64 planes for host transfers and read-back.
+//
+// One time step is ONE launch of lbm_step_kernel.  Each wavefront owns a
+// strip of 62 columns (plus one halo column on each side, lanes 0 and 63)
+// and walks down a tile of rows.  For each row it pulls the f and g
+// populations of the NEXT row (so their zeroth moments phi, psi and
+// sigma(psi) are known one row ahead), keeps a three-row window of phi,
+// psi, sigma in registers, takes the x-neighbours from adjacent lanes with
+// cross-lane moves, and so evaluates the 9-point stencils without LDS or
+// barriers.  The h populations and the previous level are read for the
+// current row only, and the 26 post-collision populations are written once.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm.h"
+#include "lbm_device.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kStrip = kWave - 2;  // interior columns per wavefront
+constexpr int kWavesPerBlock = 4;
+constexpr int kPlanes = 26;
+constexpr int kAux = 6;
+constexpr int kScratch = 8;
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceVals = 8;
+
+// D2Q9 tables for the per-site (non-sliding) kernels.
+__constant__ int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+template <class R>
+struct StepArgs {
+  Phys<R> p;
+  const void *src;
+  void *dst;
+  void *aux;
+  int *flag;
+  long long plane;
+  int nx, ny, walls;
+  int nstrips, ntiles, rows;
+};
+
+// Row offsets and wall flags for pulling row y.
+struct RowIdx {
+  long long rc, rm, rp;  // offsets of rows y, y-1, y+1 (valid even at walls)
+  bool bot, top;         // row y touches the bottom / top wall
+};
+
+__device__ __forceinline__ RowIdx row_index(int y, int nx, int ny, int walls) {
+  RowIdx r;
+  int ym = y - 1, yp = y + 1;
+  r.bot = walls && y == 0;
+  r.top = walls && y == ny - 1;
+  if (ym < 0) ym = walls ? y : ym + ny;
+  if (yp >= ny) yp = walls ? y : yp - ny;
+  r.rc = (long long)y * nx;
+  r.rm = (long long)ym * nx;
+  r.rp = (long long)yp * nx;
+  return r;
+}
+
+// Pull streaming of one 9-population field to site (x, row): population i
+// comes from x - c_i; across a wall it is the opposite population of the
+// site itself (half-way bounce-back, no flux).
+template <class S, class R>
+__device__ __forceinline__ void pull9(const S *__restrict__ s, long long pl,
+                                      const RowIdx &r, int x, int xm, int xp,
+                                      R *f) {
+  f[0] = R(s[r.rc + x]);
+  f[1] = R(s[pl + r.rc + xm]);
+  f[2] = R(r.bot ? s[4 * pl + r.rc + x] : s[2 * pl + r.rm + x]);
+  f[3] = R(s[3 * pl + r.rc + xp]);
+  f[4] = R(r.top ? s[2 * pl + r.rc + x] : s[4 * pl + r.rp + x]);
+  f[5] = R(r.bot ? s[7 * pl + r.rc + x] : s[5 * pl + r.rm + xm]);
+  f[6] = R(r.bot ? s[8 * pl + r.rc + x] : s[6 * pl + r.rm + xp]);
+  f[7] = R(r.top ? s[5 * pl + r.rc + x] : s[7 * pl + r.rp + xp]);
+  f[8] = R(r.top ? s[6 * pl + r.rc + x] : s[8 * pl + r.rp + xm]);
+}
+
+// Pull of h_1..h_8 (planes 18-25); across a wall, bounce-back with Ladd's
+// moving-wall term 2 w_i rho_w (c_i.u_w)/c_s^2 = rho_w c_ix u_w / 6 for the
+// diagonal populations (rho_w = rho at the site at collision time).
+template <class S, class R>
+__device__ __forceinline__ void pull_h(const S *__restrict__ s0, long long pl,
+                                       const RowIdx &r, int x, int xm, int xp,
+                                       R rho_w, R uwb, R uwt, R *h) {
+  const S *s = s0 + 18 * pl;  // s[(i-1) pl] is h_i
+  const R kb = rho_w * uwb * R(1.0 / 6.0), kt = rho_w * uwt * R(1.0 / 6.0);
+  h[0] = R(s[r.rc + xm]);
+  h[1] = R(r.bot ? s[3 * pl + r.rc + x] : s[pl + r.rm + x]);
+  h[2] = R(s[2 * pl + r.rc + xp]);
+  h[3] = R(r.top ? s[pl + r.rc + x] : s[3 * pl + r.rp + x]);
+  h[4] = r.bot ? R(s[6 * pl + r.rc + x]) + kb : R(s[4 * pl + r.rm + xm]);
+  h[5] = r.bot ? R(s[7 * pl + r.rc + x]) - kb : R(s[5 * pl + r.rm + xp]);
+  h[6] = r.top ? R(s[4 * pl + r.rc + x]) - kt : R(s[6 * pl + r.rp + xp]);
+  h[7] = r.top ? R(s[5 * pl + r.rc + x]) + kt : R(s[7 * pl + r.rp + xm]);
+}
+
+template <class R>
+__device__ __forceinline__ R sum9(const R *f) {
+  return ((f[0] + (f[1] + f[2])) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
+}
+
+// Value of lane-1 / lane+1 of the wavefront.
+template <class R>
+__device__ __forceinline__ R from_left(R v) {
+  return __shfl_up(v, 1, kWave);
+}
+template <class R>
+__device__ __forceinline__ R from_right(R v) {
+  return __shfl_down(v, 1, kWave);
+}
+
+template <class R>
+__device__ __forceinline__ Nine<R> window(R m, R c, R n) {
+  Nine<R> v;
+  v.m = m;
+  v.c = c;
+  v.n = n;
+  v.mL = from_left(m);
+  v.mR = from_right(m);
+  v.cL = from_left(c);
+  v.cR = from_right(c);
+  v.nL = from_left(n);
+  v.nR = from_right(n);
+  return v;
+}
+
+// The fused step: pull-stream + boundaries, phi/psi/sigma, stencils, forces,
+// closures, three MRT collisions, store.  See the file header.
+template <class S, class R, bool GENR, bool HAS_S>
+__global__ void __launch_bounds__(256)
+lbm_step_kernel(const StepArgs<R> a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int tile = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (tile >= a.ntiles) return;  // whole wavefronts only
+  const int nx = a.nx, ny = a.ny;
+  const int strip = tile % a.nstrips;
+  const int chunk = tile / a.nstrips;
+  const int x0 = strip * kStrip;
+  const int w = min(kStrip, nx - x0);
+  const bool interior = lane >= 1 && lane <= w;
+  int xl = x0 - 1 + min(lane, w + 1);
+  const int x = xl < 0 ? xl + nx : (xl >= nx ? xl - nx : xl);
+  const int xm = x == 0 ? nx - 1 : x - 1;
+  const int xp = x == nx - 1 ? 0 : x + 1;
+  const int y0 = chunk * a.rows;
+  const int y1 = min(y0 + a.rows, ny);
+  const long long pl = a.plane;
+  const S *__restrict__ src = static_cast<const S *>(a.src);
+  S *__restrict__ dst = static_cast<S *>(a.dst);
+  S *__restrict__ aux = static_cast<S *>(a.aux);
+  const Phys<R> &p = a.p;
+
+  R fc[9], gc[9];
+  R phc, psc, sgc, phm, psm, sgm;
+  {
+    RowIdx r = row_index(y0, nx, ny, a.walls);
+    pull9(src, pl, r, x, xm, xp, fc);
+    pull9(src + 9 * pl, pl, r, x, xm, xp, gc);
+    phc = sum9(fc);
+    psc = sum9(gc);
+    sgc = sigma_of(p, psc);
+  }
+  if (a.walls && y0 == 0) {  // mirror ghost row below the bottom wall
+    phm = phc;
+    psm = psc;
+    sgm = sgc;
+  } else {
+    R ft[9], gt[9];
+    const int ym = y0 == 0 ? ny - 1 : y0 - 1;
+    RowIdx r = row_index(ym, nx, ny, a.walls);
+    pull9(src, pl, r, x, xm, xp, ft);
+    pull9(src + 9 * pl, pl, r, x, xm, xp, gt);
+    phm = sum9(ft);
+    psm = sum9(gt);
+    sgm = sigma_of(p, psm);
+  }
+
+  for (int y = y0; y < y1; ++y) {
+    // next row: its populations are kept for the next iteration
+    R fn[9], gn[9];
+    R phn, psn, sgn;
+    const bool ghost = a.walls && y + 1 == ny;
+    if (!ghost) {
+      const int yn = y + 1 == ny ? 0 : y + 1;
+      RowIdx r = row_index(yn, nx, ny, a.walls);
+      pull9(src, pl, r, x, xm, xp, fn);
+      pull9(src + 9 * pl, pl, r, x, xm, xp, gn);
+      phn = sum9(fn);
+      psn = sum9(gn);
+      sgn = sigma_of(p, psn);
+    } else {  // mirror ghost row above the top wall
+      for (int i = 0; i < 9; ++i) fn[i] = gn[i] = R(0);
+      phn = phc;
+      psn = psc;
+      sgn = sgc;
+    }
+
+    // current row: h populations and the previous level
+    const RowIdx r = row_index(y, nx, ny, a.walls);
+    const long long k = r.rc + x;
+    const R php = R(aux[k]), psp = R(aux[pl + k]);
+    const R uxp = R(aux[2 * pl + k]), uyp = R(aux[3 * pl + k]);
+    R Sxp = R(0), Syp = R(0);
+    if (HAS_S) {
+      Sxp = R(aux[4 * pl + k]);
+      Syp = R(aux[5 * pl + k]);
+    }
+    R h[8];
+    pull_h(src, pl, r, x, xm, xp, rho_of(p, php), p.uwb, p.uwt, h);
+
+    // stencils from the register window
+    const Nine<R> vphi = window(phm, phc, phn);
+    const Nine<R> vsig = window(sgm, sgc, sgn);
+    R gfx, gfy, gsx, gsy;
+    grad9(vphi, gfx, gfy);
+    grad9(vsig, gsx, gsy);
+    const R lphi = lap9(vphi);
+
+    Front<R> s;
+    site_front<R, HAS_S>(p, s, phc, psc, sgc, gfx, gfy, lphi, gsx, gsy, h, php,
+                         psp, uxp, uyp, Sxp, Syp);
+    if (GENR) {
+      const Nine<R> vpsi = window(psm, psc, psn);
+      grad9(vpsi, s.gpx, s.gpy);
+    } else {
+      s.gpx = s.gpy = R(0);
+    }
+    collide_site<R, GENR>(p, s, fc, gc, h);
+
+    if (interior) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        dst[i * pl + k] = S(fc[i]);
+        dst[(9 + i) * pl + k] = S(gc[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dst[(18 + i) * pl + k] = S(h[i]);
+      aux[k] = S(phc);
+      aux[pl + k] = S(psc);
+      aux[2 * pl + k] = S(s.ux);
+      aux[3 * pl + k] = S(s.uy);
+      if (HAS_S) {
+        aux[4 * pl + k] = S(s.Sx);
+        aux[5 * pl + k] = S(s.Sy);
+      }
+      if (!isfinite(phc + psc + s.ux + s.uy)) *a.flag = 1;
+    }
+
+    // slide the window
+    phm = phc;
+    psm = psc;
+    sgm = sgc;
+    phc = phn;
+    psc = psn;
+    sgc = sgn;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      fc[i] = fn[i];
+      gc[i] = gn[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------ site kernels
+
+// Neighbour of site (x, y) at offset (dx, dy) in {-1,0,1}^2: periodic in x;
+// periodic in y or, between walls, the wall row itself (mirror ghost).
+__device__ __forceinline__ long long nbr_index(int x, int y, int dx, int dy,
+                                               int nx, int ny, int walls) {
+  int xx = x + dx, yy = y + dy;
+  xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+  if (walls) {
+    yy = yy < 0 ? 0 : (yy >= ny ? ny - 1 : yy);
+  } else {
+    yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+  }
+  return (long long)yy * nx + xx;
+}
+
+template <class R>
+__device__ __forceinline__ Nine<R> gather9(const R *a, int x, int y, int nx,
+                                           int ny, int walls) {
+  Nine<R> v;
+  v.mL = a[nbr_index(x, y, -1, -1, nx, ny, walls)];
+  v.m = a[nbr_index(x, y, 0, -1, nx, ny, walls)];
+  v.mR = a[nbr_index(x, y, 1, -1, nx, ny, walls)];
+  v.cL = a[nbr_index(x, y, -1, 0, nx, ny, walls)];
+  v.c = a[nbr_index(x, y, 0, 0, nx, ny, walls)];
+  v.cR = a[nbr_index(x, y, 1, 0, nx, ny, walls)];
+  v.nL = a[nbr_index(x, y, -1, 1, nx, ny, walls)];
+  v.n = a[nbr_index(x, y, 0, 1, nx, ny, walls)];
+  v.nR = a[nbr_index(x, y, 1, 1, nx, ny, walls)];
+  return v;
+}
+
+struct SiteArgs {
+  const void *src;
+  void *aux;
+  double *scratch;  // kScratch float64 planes
+  long long plane;
+  int nx, ny, walls;
+};
+
+// Initial state in float64: post-collision populations := equilibria of
+// Eqs. (22), (26), (30) with P = 0 and S of Eq. (16) from the gradient of
+// the initial phi; previous level := the initial fields.  Inputs are
+// scratch planes 0-3 (phi, psi, ux, uy).
+template <class S>
+__global__ void __launch_bounds__(256)
+lbm_init_kernel(const SiteArgs a, const Phys<double> p, S *__restrict__ dst) {
+  const long long n = (long long)a.nx * a.ny;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int x = int(k % a.nx), y = int(k / a.nx);
+  const long long pl = a.plane;
+  const double *phi0 = a.scratch, *psi0 = a.scratch + pl;
+  const double *ux0 = a.scratch + 2 * pl, *uy0 = a.scratch + 3 * pl;
+  const Nine<double> v = gather9(phi0, x, y, a.nx, a.ny, a.walls);
+  double gx, gy;
+  grad9(v, gx, gy);
+  const double phi = phi0[k], psi = psi0[k], ux = ux0[k], uy = uy0[k];
+  const double gn = sqrt(gx * gx + gy * gy);
+  const double inv = 1.0 / (gn + 1e-12);
+  const double delta = p.c4W * ((p.phiA - phi) * (phi - p.phiB));
+  const double Sx = p.Mdrho * (gx - delta * gx * inv);
+  const double Sy = p.Mdrho * (gy - delta * gy * inv);
+  const double rho = rho_of(p, phi);
+  const double jx = rho * ux, jy = rho * uy;
+  const double Ax = jx - Sx, Ay = jy - Sy, Au = Ax * ux + Ay * uy;
+  const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                       1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  for (int i = 0; i < 9; ++i) {
+    const double cu = kCx[i] * ux + kCy[i] * uy;
+    dst[i * pl + k] = S(w[i] * phi * (1.0 + 3.0 * cu));
+    dst[(9 + i) * pl + k] = S(w[i] * psi * (1.0 + 3.0 * cu));
+    if (i > 0) {
+      const double cj = kCx[i] * jx + kCy[i] * jy;
+      const double cA = kCx[i] * Ax + kCy[i] * Ay;
+      dst[(17 + i) * pl + k] = S(w[i] * (3.0 * cj + 4.5 * cA * cu - 1.5 * Au));
+    }
+  }
+  S *aux = static_cast<S *>(a.aux);
+  aux[k] = S(phi);
+  aux[pl + k] = S(psi);
+  aux[2 * pl + k] = S(ux);
+  aux[3 * pl + k] = S(uy);
+  aux[4 * pl + k] = S(Sx);
+  aux[5 * pl + k] = S(Sy);
+}
+
+// Read-back, pass 1: phi, psi, sigma of the current level into scratch
+// planes 5-7 (arithmetic type R).
+template <class S, class R>
+__global__ void __launch_bounds__(256)
+lbm_macro_scalars_kernel(const SiteArgs a, const Phys<R> p) {
+  const long long n = (long long)a.nx * a.ny;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int x = int(k % a.nx), y = int(k / a.nx);
+  const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
+  const S *src = static_cast<const S *>(a.src);
+  const long long pl = a.plane;
+  const RowIdx r = row_index(y, a.nx, a.ny, a.walls);
+  R f[9], g[9];
+  pull9(src, pl, r, x, xm, xp, f);
+  pull9(src + 9 * pl, pl, r, x, xm, xp, g);
+  R *out = reinterpret_cast<R *>(a.scratch + 5 * pl);
+  const R phi = sum9(f), psi = sum9(g);
+  out[k] = phi;
+  out[pl + k] = psi;
+  out[2 * pl + k] = sigma_of(p, psi);
+}
+
+// Read-back, pass 2: u and P by the same closures as the step, float64
+// phi, psi, ux, uy, P into scratch planes 0-4.
+template <class S, class R, bool HAS_S>
+__global__ void __launch_bounds__(256)
+lbm_macro_fields_kernel(const SiteArgs a, const Phys<R> p) {
+  const long long n = (long long)a.nx * a.ny;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int x = int(k % a.nx), y = int(k / a.nx);
+  const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
+  const S *src = static_cast<const S *>(a.src);
+  const S *aux = static_cast<const S *>(a.aux);
+  const long long pl = a.plane;
+  const R *sc = reinterpret_cast<const R *>(a.scratch + 5 * pl);
+  const Nine<R> vphi = gather9(sc, x, y, a.nx, a.ny, a.walls);
+  const Nine<R> vsig = gather9(sc + 2 * pl, x, y, a.nx, a.ny, a.walls);
+  R gfx, gfy, gsx, gsy;
+  grad9(vphi, gfx, gfy);
+  grad9(vsig, gsx, gsy);
+  const R lphi = lap9(vphi);
+  const R php = R(aux[k]), psp = R(aux[pl + k]);
+  const R uxp = R(aux[2 * pl + k]), uyp = R(aux[3 * pl + k]);
+  const R Sxp = HAS_S ? R(aux[4 * pl + k]) : R(0);
+  const R Syp = HAS_S ? R(aux[5 * pl + k]) : R(0);
+  const RowIdx r = row_index(y, a.nx, a.ny, a.walls);
+  R h[8];
+  pull_h(src, pl, r, x, xm, xp, rho_of(p, php), p.uwb, p.uwt, h);
+  Front<R> s;
+  site_front<R, HAS_S>(p, s, vphi.c, sc[pl + k], vsig.c, gfx, gfy, lphi, gsx,
+                       gsy, h, php, psp, uxp, uyp, Sxp, Syp);
+  a.scratch[k] = double(s.phi);
+  a.scratch[pl + k] = double(s.psi);
+  a.scratch[2 * pl + k] = double(s.ux);
+  a.scratch[3 * pl + k] = double(s.uy);
+  a.scratch[4 * pl + k] = double(s.P);
+}
+
+// Float64 reductions over scratch planes 0-3 (phi, psi, ux, uy): per-block
+// partial sums in a fixed order (wavefront shuffles, then LDS), then one
+// block adds the partials in a fixed order.  Deterministic.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, kWave));
+  return v;
+}
+
+__global__ void __launch_bounds__(256)
+lbm_reduce_kernel(const SiteArgs a, const Phys<double> p, double *partials) {
+  const long long n = (long long)a.nx * a.ny;
+  const long long pl = a.plane;
+  double acc[kReduceVals] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    const double phi = a.scratch[k], psi = a.scratch[pl + k];
+    const double ux = a.scratch[2 * pl + k], uy = a.scratch[3 * pl + k];
+    const double rho = rho_of(p, phi);
+    const double u2 = ux * ux + uy * uy;
+    acc[0] += phi;
+    acc[1] += psi;
+    acc[2] += rho * ux;
+    acc[3] += rho * uy;
+    acc[4] += 0.5 * rho * u2;
+    acc[5] = fmax(acc[5], sqrt(u2));
+    if (!isfinite(phi + psi + ux + uy)) acc[6] = 1.0;
+  }
+  __shared__ double lds[kReduceVals][256 / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+  for (int j = 0; j < 7; ++j) {
+    const double v = (j == 5 || j == 6) ? wave_max(acc[j]) : wave_sum(acc[j]);
+    if (lane == 0) lds[j][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int j = threadIdx.x;
+    double v = lds[j][0];
+    for (int q = 1; q < 256 / kWave; ++q)
+      v = (j == 5 || j == 6) ? fmax(v, lds[j][q]) : v + lds[j][q];
+    partials[blockIdx.x * kReduceVals + j] = v;
+  }
+}
+
+__global__ void __launch_bounds__(64)
+lbm_reduce_final_kernel(const double *partials, int nblocks, double *out) {
+  if (threadIdx.x >= 7) return;
+  const int j = threadIdx.x;
+  double v = partials[j];
+  for (int b = 1; b < nblocks; ++b) {
+    const double q = partials[b * kReduceVals + j];
+    v = (j == 5 || j == 6) ? fmax(v, q) : v + q;
+  }
+  out[j] = v;
+}
+
+// ------------------------------------------------------------------ host
+
+enum Prec { kF64 = LBM_FP64, kF32 = LBM_FP32, kF16 = LBM_FP16DEV };
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  long long plane;  // elements per plane
+  size_t pop_bytes, aux_bytes, scratch_bytes, partial_bytes, flag_bytes;
+  size_t off_pop[2], off_aux, off_scratch, off_partial, off_flag, total;
+};
+
+size_t storage_size(int prec) { return prec == kF64 ? 8 : (prec == kF32 ? 4 : 2); }
+size_t aux_size(int prec) { return prec == kF64 ? 8 : 4; }
+
+Layout make_layout(const lbm_params &p) {
+  Layout L;
+  const long long n = (long long)p.nx * p.ny;
+  L.plane = (long long)align_up((size_t)n, 64);
+  L.pop_bytes = align_up((size_t)kPlanes * L.plane * storage_size(p.precision), 256);
+  L.aux_bytes = align_up((size_t)kAux * L.plane * aux_size(p.precision), 256);
+  L.scratch_bytes = align_up((size_t)kScratch * L.plane * 8, 256);
+  L.partial_bytes = align_up((size_t)(kReduceBlocks + 1) * kReduceVals * 8, 256);
+  L.flag_bytes = 256;
+  size_t o = 0;
+  L.off_pop[0] = o;
+  o += L.pop_bytes;
+  L.off_pop[1] = o;
+  o += L.pop_bytes;
+  L.off_aux = o;
+  o += L.aux_bytes;
+  L.off_scratch = o;
+  o += L.scratch_bytes;
+  L.off_partial = o;
+  o += L.partial_bytes;
+  L.off_flag = o;
+  o += L.flag_bytes;
+  L.total = o;
+  return L;
+}
+
+std::string g_create_error;
+
+const char *validate(const lbm_params *p) {
+  if (!p) return "params is NULL";
+  if (p->nx < 3 || p->ny < 3) return "nx and ny must be >= 3";
+  if ((long long)p->nx * p->ny > (1LL << 31)) return "grid too large";
+  if (p->walls_y != 0 && p->walls_y != 1) return "walls_y must be 0 or 1";
+  if (p->eos != LBM_EOS_LINEAR && p->eos != LBM_EOS_LANGMUIR) return "unknown eos";
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32) {
+    if (p->precision == LBM_FP16DEV) return "FP16-deviation storage is not available";
+    return "unknown precision";
+  }
+  if (p->reserved != 0) return "reserved must be 0";
+  if (!(p->phiA > p->phiB)) return "phiA must exceed phiB";
+  if (!(p->W > 0)) return "W must be > 0";
+  if (!(p->M > 0) || !(p->D > 0)) return "M and D must be > 0 (tau > 1/2)";
+  if (!(p->rhoA > 0) || !(p->rhoB > 0)) return "densities must be > 0";
+  if (!(p->muA > 0) || !(p->muB > 0)) return "viscosities must be > 0";
+  if (!(p->r >= 0)) return "r must be >= 0";
+  if (!(p->sigma0 >= 0)) return "sigma0 must be >= 0";
+  const double fin[] = {p->u_wall_bot, p->u_wall_top, p->beta, p->gx, p->gy};
+  for (double v : fin)
+    if (!std::isfinite(v)) return "non-finite parameter";
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      if (!(p->s_free[a][b] > 0 && p->s_free[a][b] < 2)) return "free rates must lie in (0, 2)";
+  return nullptr;
+}
+
+template <class R>
+Phys<R> make_phys(const lbm_params &q) {
+  Phys<R> p;
+  const double dphi = q.phiA - q.phiB;
+  const double drho = (q.rhoA - q.rhoB) / dphi;
+  p.phiA = R(q.phiA);
+  p.phiB = R(q.phiB);
+  p.phiAB = R(q.phiA + q.phiB);
+  p.c4W = R(4.0 / (q.W * dphi));
+  p.cbulk = R(24.0 / (q.W * dphi * dphi * dphi * dphi));
+  p.cW = R(1.5 * q.W / (dphi * dphi));
+  p.rhoB = R(q.rhoB);
+  p.drho = R(drho);
+  p.muB = R(q.muB);
+  p.dmu = R((q.muA - q.muB) / dphi);
+  p.Mdrho = R(q.M * drho);
+  p.gx = R(q.gx);
+  p.gy = R(q.gy);
+  p.sigma0 = R(q.sigma0);
+  p.beta = R(q.beta);
+  p.r = R(q.r);
+  p.rm1 = R(q.r - 1.0);
+  p.s1f = R(1.0 / (3.0 * q.M + 0.5));
+  p.s2f = R(q.s_free[0][0]);
+  p.s3f = R(q.s_free[0][1]);
+  p.s4f = R(q.s_free[0][2]);
+  p.s1g = R(1.0 / (3.0 * q.D + 0.5));
+  p.s2g = R(q.s_free[1][0]);
+  p.s3g = R(q.s_free[1][1]);
+  p.s4g = R(q.s_free[1][2]);
+  p.s3h = R(q.s_free[2][1]);
+  p.s4h = R(q.s_free[2][2]);
+  p.uwb = R(q.u_wall_bot);
+  p.uwt = R(q.u_wall_top);
+  p.psi_max = R(1.0 - 1e-9);
+  p.eos = q.eos;
+  return p;
+}
+
+}  // namespace
+
+struct lbm_handle {
+  lbm_params p;
+  Layout L;
+  hipStream_t stream;
+  char *ws;
+  int cur;
+  int64_t step;
+  bool valid;
+  int rows;
+  bool genr, has_s;
+  std::string err;
+};
+
+namespace {
+
+lbm_status fail(lbm_handle *h, lbm_status s, const std::string &msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_create_error = msg;
+  return s;
+}
+
+lbm_status hip_check(lbm_handle *h, hipError_t e, const char *what) {
+  if (e == hipSuccess) return LBM_OK;
+  return fail(h, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *pops(lbm_handle *h, int which) { return h->ws + h->L.off_pop[which]; }
+void *auxp(lbm_handle *h) { return h->ws + h->L.off_aux; }
+double *scratch(lbm_handle *h) { return reinterpret_cast<double *>(h->ws + h->L.off_scratch); }
+double *partials(lbm_handle *h) { return reinterpret_cast<double *>(h->ws + h->L.off_partial); }
+int *flagp(lbm_handle *h) { return reinterpret_cast<int *>(h->ws + h->L.off_flag); }
+
+SiteArgs site_args(lbm_handle *h) {
+  SiteArgs a;
+  a.src = pops(h, h->cur);
+  a.aux = auxp(h);
+  a.scratch = scratch(h);
+  a.plane = h->L.plane;
+  a.nx = h->p.nx;
+  a.ny = h->p.ny;
+  a.walls = h->p.walls_y;
+  return a;
+}
+
+int default_rows(const lbm_params &p) {
+  const long long strips = (p.nx + kStrip - 1) / kStrip;
+  // aim for at least ~8192 wavefronts in flight on large grids, but keep
+  // tiles tall enough that the two extra halo rows stay a small overhead
+  long long rows = strips * p.ny / 8192;
+  if (rows < 8) rows = 8;
+  if (rows > 64) rows = 64;
+  return int(rows);
+}
+
+template <class S, class R, bool GENR, bool HAS_S>
+hipError_t launch_step(lbm_handle *h) {
+  StepArgs<R> a;
+  a.p = make_phys<R>(h->p);
+  a.src = pops(h, h->cur);
+  a.dst = pops(h, h->cur ^ 1);
+  a.aux = auxp(h);
+  a.flag = flagp(h);
+  a.plane = h->L.plane;
+  a.nx = h->p.nx;
+  a.ny = h->p.ny;
+  a.walls = h->p.walls_y;
+  a.nstrips = (h->p.nx + kStrip - 1) / kStrip;
+  a.rows = h->rows;
+  a.ntiles = a.nstrips * ((h->p.ny + a.rows - 1) / a.rows);
+  const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  hipLaunchKernelGGL((lbm_step_kernel<S, R, GENR, HAS_S>), dim3(blocks),
+                     dim3(kWave * kWavesPerBlock), 0, h->stream, a);
+  return hipGetLastError();
+}
+
+template <class S, class R>
+hipError_t launch_step_prec(lbm_handle *h) {
+  if (h->genr)
+    return h->has_s ? launch_step<S, R, true, true>(h) : launch_step<S, R, true, false>(h);
+  return h->has_s ? launch_step<S, R, false, true>(h) : launch_step<S, R, false, false>(h);
+}
+
+template <class S, class R>
+hipError_t launch_macros(lbm_handle *h) {
+  SiteArgs a = site_args(h);
+  const long long n = (long long)h->p.nx * h->p.ny;
+  const int blocks = int((n + 255) / 256);
+  const Phys<R> p = make_phys<R>(h->p);
+  hipLaunchKernelGGL((lbm_macro_scalars_kernel<S, R>), dim3(blocks), dim3(256), 0,
+                     h->stream, a, p);
+  if (h->has_s)
+    hipLaunchKernelGGL((lbm_macro_fields_kernel<S, R, true>), dim3(blocks), dim3(256),
+                       0, h->stream, a, p);
+  else
+    hipLaunchKernelGGL((lbm_macro_fields_kernel<S, R, false>), dim3(blocks), dim3(256),
+                       0, h->stream, a, p);
+  return hipGetLastError();
+}
+
+hipError_t run_macros(lbm_handle *h) {
+  return h->p.precision == kF64 ? launch_macros<double, double>(h)
+                                : launch_macros<float, float>(h);
+}
+
+// Reads the sticky device flag (synchronising); marks the state invalid.
+lbm_status check_flag(lbm_handle *h) {
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, flagp(h), sizeof(int), hipMemcpyDeviceToHost,
+                                h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_check(h, e, "reading the non-finite flag");
+  if (flag) {
+    h->valid = false;
+    return fail(h, LBM_ENONFINITE, "the device produced a non-finite value");
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params *params) {
+  if (validate(params)) return 0;
+  return make_layout(*params).total;
+}
+
+lbm_status lbm_create(const lbm_params *params, void *dev_ws, size_t ws_bytes,
+                      void *hip_stream, lbm_handle **out) {
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (const char *m = validate(params)) return fail(nullptr, LBM_EINVAL, m);
+  const Layout L = make_layout(*params);
+  if (!dev_ws) return fail(nullptr, LBM_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_ws) % 256)
+    return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(nullptr, LBM_ENOMEM, "workspace too small");
+  lbm_handle *h = new (std::nothrow) lbm_handle();
+  if (!h) return fail(nullptr, LBM_ENOMEM, "out of host memory");
+  h->p = *params;
+  h->L = L;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char *>(dev_ws);
+  h->cur = 0;
+  h->step = 0;
+  h->valid = false;
+  h->rows = default_rows(*params);
+  h->genr = params->r != 1.0;
+  h->has_s = params->rhoA != params->rhoB;
+  *out = h;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_handle *h, const double *phi, const double *psi,
+                           const double *ux, const double *uy) {
+  if (!h) return LBM_EINVAL;
+  if (!phi || !psi || !ux || !uy) return fail(h, LBM_EINVAL, "NULL field");
+  const long long n = (long long)h->p.nx * h->p.ny;
+  for (long long k = 0; k < n; ++k) {
+    if (!std::isfinite(phi[k]) || !std::isfinite(psi[k]) || !std::isfinite(ux[k]) ||
+        !std::isfinite(uy[k]))
+      return fail(h, LBM_EINVAL, "non-finite initial value");
+    if (h->p.eos == LBM_EOS_LANGMUIR && psi[k] >= 1.0)
+      return fail(h, LBM_EINVAL, "Langmuir EOS needs psi < 1");
+  }
+  double *sc = scratch(h);
+  const long long pl = h->L.plane;
+  const double *src[4] = {phi, psi, ux, uy};
+  for (int j = 0; j < 4; ++j) {
+    hipError_t e = hipMemcpyAsync(sc + j * pl, src[j], n * sizeof(double),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_check(h, e, "copying initial fields");
+  }
+  SiteArgs a = site_args(h);
+  const Phys<double> p = make_phys<double>(h->p);
+  const int blocks = int((n + 255) / 256);
+  h->cur = 0;
+  if (h->p.precision == kF64)
+    hipLaunchKernelGGL((lbm_init_kernel<double>), dim3(blocks), dim3(256), 0,
+                       h->stream, a, p, static_cast<double *>(pops(h, 0)));
+  else
+    hipLaunchKernelGGL((lbm_init_kernel<float>), dim3(blocks), dim3(256), 0,
+                       h->stream, a, p, static_cast<float *>(pops(h, 0)));
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemsetAsync(flagp(h), 0, sizeof(int), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_check(h, e, "initialising");
+  h->step = 0;
+  h->valid = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_handle *h, int64_t nsteps) {
+  if (!h) return LBM_EINVAL;
+  if (nsteps < 0) return fail(h, LBM_EINVAL, "nsteps < 0");
+  if (!h->valid) return fail(h, LBM_ESTATE, "no valid state");
+  for (int64_t t = 0; t < nsteps; ++t) {
+    hipError_t e = h->p.precision == kF64 ? launch_step_prec<double, double>(h)
+                                          : launch_step_prec<float, float>(h);
+    if (e != hipSuccess) return hip_check(h, e, "launching the step kernel");
+    h->cur ^= 1;
+    h->step += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_read_fields(lbm_handle *h, double *phi, double *psi, double *ux,
+                           double *uy, double *P) {
+  if (!h) return LBM_EINVAL;
+  if (!h->valid) return fail(h, LBM_ESTATE, "no valid state");
+  lbm_status st = check_flag(h);
+  if (st != LBM_OK) return st;
+  hipError_t e = run_macros(h);
+  if (e != hipSuccess) return hip_check(h, e, "launching read-back kernels");
+  const long long n = (long long)h->p.nx * h->p.ny;
+  double *dst[5] = {phi, psi, ux, uy, P};
+  for (int j = 0; j < 5; ++j) {
+    if (!dst[j]) continue;
+    e = hipMemcpyAsync(dst[j], scratch(h) + j * h->L.plane, n * sizeof(double),
+                       hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_check(h, e, "copying fields");
+  }
+  e = hipStreamSynchronize(h->stream);
+  return hip_check(h, e, "reading fields");
+}
+
+lbm_status lbm_moments(lbm_handle *h, lbm_moments_t *out) {
+  if (!h) return LBM_EINVAL;
+  if (!out) return fail(h, LBM_EINVAL, "out is NULL");
+  if (!h->valid) return fail(h, LBM_ESTATE, "no valid state");
+  lbm_status st = check_flag(h);
+  if (st != LBM_OK) return st;
+  hipError_t e = run_macros(h);
+  if (e != hipSuccess) return hip_check(h, e, "launching read-back kernels");
+  SiteArgs a = site_args(h);
+  const Phys<double> p = make_phys<double>(h->p);
+  double *part = partials(h);
+  hipLaunchKernelGGL(lbm_reduce_kernel, dim3(kReduceBlocks), dim3(256), 0, h->stream,
+                     a, p, part);
+  hipLaunchKernelGGL(lbm_reduce_final_kernel, dim3(1), dim3(64), 0, h->stream,
+                     (const double *)part, kReduceBlocks, part + kReduceBlocks * kReduceVals);
+  e = hipGetLastError();
+  double v[kReduceVals];
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(v, part + kReduceBlocks * kReduceVals, sizeof v,
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_check(h, e, "reducing");
+  out->step = h->step;
+  out->sum_phi = v[0];
+  out->sum_psi = v[1];
+  out->mom_x = v[2];
+  out->mom_y = v[3];
+  out->kinetic = v[4];
+  out->max_u = v[5];
+  out->nonfinite = v[6] != 0.0;
+  out->pad = 0;
+  if (out->nonfinite) {
+    h->valid = false;
+    return fail(h, LBM_ENONFINITE, "non-finite macroscopic field");
+  }
+  return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_handle *h) {
+  if (!h) return 0;
+  return sizeof(int64_t) + h->L.pop_bytes + h->L.aux_bytes;
+}
+
+lbm_status lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
+  if (!h) return LBM_EINVAL;
+  if (!host_buf || bytes != lbm_state_bytes(h)) return fail(h, LBM_EINVAL, "bad buffer");
+  if (!h->valid) return fail(h, LBM_ESTATE, "no valid state");
+  lbm_status st = check_flag(h);
+  if (st != LBM_OK) return st;
+  char *b = static_cast<char *>(host_buf);
+  std::memcpy(b, &h->step, sizeof(int64_t));
+  hipError_t e = hipMemcpyAsync(b + sizeof(int64_t), pops(h, h->cur), h->L.pop_bytes,
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b + sizeof(int64_t) + h->L.pop_bytes, auxp(h), h->L.aux_bytes,
+                       hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  return hip_check(h, e, "saving state");
+}
+
+lbm_status lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
+  if (!h) return LBM_EINVAL;
+  if (!host_buf || bytes != lbm_state_bytes(h)) return fail(h, LBM_EINVAL, "bad buffer");
+  const char *b = static_cast<const char *>(host_buf);
+  int64_t step;
+  std::memcpy(&step, b, sizeof(int64_t));
+  h->cur = 0;
+  hipError_t e = hipMemcpyAsync(pops(h, 0), b + sizeof(int64_t), h->L.pop_bytes,
+                                hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(auxp(h), b + sizeof(int64_t) + h->L.pop_bytes, h->L.aux_bytes,
+                       hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(flagp(h), 0, sizeof(int), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_check(h, e, "restoring state");
+  h->step = step;
+  h->valid = true;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_handle *h) { delete h; }
+
+const char *lbm_last_error(const lbm_handle *h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+lbm_status lbm_set_tile_rows(lbm_handle *h, int32_t rows) {
+  if (!h) return LBM_EINVAL;
+  if (rows < 0 || rows > 4096) return fail(h, LBM_EINVAL, "rows out of range");
+  h->rows = rows == 0 ? default_rows(h->p) : rows;
+  return LBM_OK;
+}
+
+const char *lbm_step_kernel_name(const lbm_handle *h) {
+  (void)h;
+  return "lbm_step_kernel";
+}
+
+}  // extern "C"

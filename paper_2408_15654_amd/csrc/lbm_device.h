@@ -1,0 +1,279 @@
+// Device-side per-site arithmetic of the coupled three-field lattice
+// Boltzmann step (Zhan, Liang, Chai, Shi, arXiv:2408.15654), templated on
+// the arithmetic type R (float or double).
+//
+// Lattice: D2Q9, c_0..c_8 = (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1)
+// (-1,-1) (1,-1) (the order of the rows of M in Eq. (34)), weights 4/9,
+// 1/9, 1/36, c_s^2 = 1/3, lattice units.
+//
+// The collisions are done in raw-moment space (Sec. 4): the nine moments of
+// Eq. (34) are formed with shared partial sums, the equilibrium and source
+// moments are their closed forms, and the inverse transform is applied
+// explicitly.  h_0 is never formed: column 0 of M is e_0 and rows 1-8 of
+// M^-1 have a zero first entry, so h_0 feeds nothing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lbm {
+
+// Parameters of the physics, pre-combined on the host.
+template <class R>
+struct Phys {
+  R phiA, phiB, phiAB;     // phiA, phiB, phiA + phiB
+  R c4W;                   // 4 / (W dphi): delta = c4W (phiA-phi)(phi-phiB)
+  R cbulk;                 // 24 / (W dphi^4): bulk part of mu_phi
+  R cW;                    // 3 W / (2 dphi^2): gradient part and Marangoni
+  R rhoB, drho;            // rho = rhoB + drho (phi - phiB)
+  R muB, dmu;              // mu  = muB  + dmu  (phi - phiB)
+  R Mdrho;                 // M drho: S = Mdrho (grad phi - delta n)
+  R gx, gy;                // body force per unit mass
+  R sigma0, beta;          // equation of state
+  R r, rm1;                // r and r - 1
+  R s1f, s2f, s3f, s4f;    // rates of the phase-field LB
+  R s1g, s2g, s3g, s4g;    // rates of the surfactant LB
+  R s3h, s4h;              // free rates of the flow LB (s2 is per site)
+  R uwb, uwt;              // wall speeds (bottom, top)
+  R psi_max;               // Langmuir clamp 1 - 1e-9
+  int eos;                 // 0 linear, 1 Langmuir
+};
+
+template <class R>
+__device__ __forceinline__ R rho_of(const Phys<R>& p, R phi) {
+  return p.rhoB + p.drho * (phi - p.phiB);
+}
+
+// Eq. (20) (linear) or Eq. (19) (Langmuir).
+template <class R>
+__device__ __forceinline__ R sigma_of(const Phys<R>& p, R psi) {
+  if (p.eos == 1) {
+    R q = psi < p.psi_max ? psi : p.psi_max;
+    return p.sigma0 * (R(1) + p.beta * log(R(1) - q));
+  }
+  return p.sigma0 - p.sigma0 * p.beta * psi;
+}
+
+// Isotropic D2Q9 stencil values of one scalar around a site: m = row y-1,
+// c = row y, n = row y+1; L = column x-1, R = column x+1.
+template <class R>
+struct Nine {
+  R mL, m, mR, cL, c, cR, nL, n, nR;
+};
+
+// grad X = sum_i w_i c_i X(x + c_i) / c_s^2.
+template <class R>
+__device__ __forceinline__ void grad9(const Nine<R>& v, R& gx, R& gy) {
+  const R third = R(1) / R(3), twelfth = R(1) / R(12);
+  gx = third * (v.cR - v.cL) + twelfth * ((v.nR - v.nL) + (v.mR - v.mL));
+  gy = third * (v.n - v.m) + twelfth * ((v.nR + v.nL) - (v.mR + v.mL));
+}
+
+// lap X = sum_i 2 w_i (X(x + c_i) - X(x)) / c_s^2.
+template <class R>
+__device__ __forceinline__ R lap9(const Nine<R>& v) {
+  const R a = R(2) / R(3), b = R(1) / R(6), c = R(10) / R(3);
+  return a * ((v.cR + v.cL) + (v.n + v.m)) + b * ((v.nR + v.nL) + (v.mR + v.mL)) -
+         c * v.c;
+}
+
+// Everything the closures and the sources need at one site.
+template <class R>
+struct Front {
+  R phi, psi, rho;
+  R ux, uy, jx, jy;       // u and rho u
+  R Sx, Sy;               // mass flux, Eq. (16)
+  R Fx, Fy;               // total force
+  R grx, gry;             // grad rho
+  R nx, ny, delta, a;     // normal, Eq. (8) delta and a = d delta/d phi
+  R gpx, gpy;             // grad psi (general r)
+  R P;                    // pressure, Eq. (32b)
+  R dpux, dpuy;           // d_t(phi u)
+  R dqux, dquy;           // d_t(psi u)
+  R dTxx, dTxy, dTyy;     // d_t(rho uu - (Su + uS)/2)
+  R s2h;                  // viscous rate, Eq. (33)
+};
+
+// Forces, closures and time differences at one site, from the stencils
+// (grad phi, lap phi, grad sigma, grad psi), sigma, the post-stream h_1..h_8
+// and the previous level (phi, psi, u, S).  Eqs. (8), (15), (16), (18),
+// (32a) read as rho u = sum c_i h_i + F/2, (32b) with K = 2/3.
+template <class R, bool HAS_S>
+__device__ __forceinline__ void site_front(const Phys<R>& p, Front<R>& s, R phi,
+                                           R psi, R sig, R gfx, R gfy, R lphi,
+                                           R gsx, R gsy, const R* h, R php,
+                                           R psp, R uxp, R uyp, R Sxp, R Syp) {
+  s.phi = phi;
+  s.psi = psi;
+  const R gn2 = gfx * gfx + gfy * gfy;
+  const R gn = sqrt(gn2);
+  const R inv = R(1) / (gn + R(1e-12));
+  s.nx = gfx * inv;
+  s.ny = gfy * inv;
+  const R qa = p.phiA - phi, qb = phi - p.phiB, qab = p.phiAB - phi - phi;
+  s.delta = p.c4W * (qa * qb);
+  s.a = p.c4W * qab;
+  // capillary force sigma mu_phi grad phi plus Marangoni force, Eq. (18)
+  const R muphi = p.cbulk * (qa * qb * qab) - p.cW * lphi;
+  const R sdp = gsx * gfx + gsy * gfy;
+  const R rho = rho_of(p, phi);
+  s.rho = rho;
+  s.Fx = sig * muphi * gfx + p.cW * (gn2 * gsx - sdp * gfx) + rho * p.gx;
+  s.Fy = sig * muphi * gfy + p.cW * (gn2 * gsy - sdp * gfy) + rho * p.gy;
+  if (HAS_S) {
+    s.Sx = p.Mdrho * (gfx - s.delta * s.nx);
+    s.Sy = p.Mdrho * (gfy - s.delta * s.ny);
+    s.grx = p.drho * gfx;
+    s.gry = p.drho * gfy;
+  } else {
+    s.Sx = s.Sy = s.grx = s.gry = R(0);
+  }
+  // first moment and sum of h_1..h_8 (h[k] holds h_{k+1})
+  const R d57 = h[4] - h[6], d68 = h[5] - h[7];
+  const R jx0 = (h[0] - h[2]) + (d57 - d68);
+  const R jy0 = (h[1] - h[3]) + (d57 + d68);
+  const R sumh = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
+  s.jx = jx0 + R(0.5) * s.Fx;
+  s.jy = jy0 + R(0.5) * s.Fy;
+  const R irho = R(1) / rho;
+  s.ux = s.jx * irho;
+  s.uy = s.jy * irho;
+  const R ux = s.ux, uy = s.uy;
+  // backward time differences against the previous level
+  s.dpux = phi * ux - php * uxp;
+  s.dpuy = phi * uy - php * uyp;
+  s.dqux = psi * ux - psp * uxp;
+  s.dquy = psi * uy - psp * uyp;
+  const R rhop = rho_of(p, php);
+  R Txx = rho * ux * ux, Txy = rho * ux * uy, Tyy = rho * uy * uy;
+  R Txxp = rhop * uxp * uxp, Txyp = rhop * uxp * uyp, Tyyp = rhop * uyp * uyp;
+  if (HAS_S) {
+    Txx -= s.Sx * ux;
+    Tyy -= s.Sy * uy;
+    Txy -= R(0.5) * (s.Sx * uy + ux * s.Sy);
+    Txxp -= Sxp * uxp;
+    Tyyp -= Syp * uyp;
+    Txyp -= R(0.5) * (Sxp * uyp + uxp * Syp);
+  }
+  s.dTxx = Txx - Txxp;
+  s.dTxy = Txy - Txyp;
+  s.dTyy = Tyy - Tyyp;
+  // Eq. (32b): P = c_s^2/(1-w0) [sum_{i!=0} h_i + u.grad rho/2
+  //            - w0 (rho u - S).u/(2 c_s^2) + K/2 d_t(rho u.u - S.u)]
+  const R udr = ux * s.grx + uy * s.gry;
+  const R Au = (s.jx - s.Sx) * ux + (s.jy - s.Sy) * uy;
+  s.P = R(0.6) * (sumh + R(0.5) * udr - R(2) / R(3) * Au +
+                  R(1) / R(3) * (s.dTxx + s.dTyy));
+  // Eq. (33): 1/s2 = 3 mu/rho + 1/2
+  const R mu = p.muB + p.dmu * (phi - p.phiB);
+  s.s2h = R(1) / (R(3) * mu * irho + R(0.5));
+}
+
+// MRT collision of a convection-diffusion LB (Eqs. (21), (25)) in raw-moment
+// space.  Equilibrium w_i X (1 + 3 c_i.u); source w_i c_i.V with
+// V = 3 d_t(X u) + (flux term); rates s1 (first moments), s2 (second), s3
+// (third), s4 (fourth).  In place on f[0..8].
+template <class R>
+__device__ __forceinline__ void collide_cde(R* f, R X, R ux, R uy, R Vx, R Vy,
+                                            R s1, R s2, R s3, R s4) {
+  const R a57 = f[5] + f[7], a68 = f[6] + f[8];
+  const R d57 = f[5] - f[7], d68 = f[6] - f[8];
+  R m5 = a57 - a68, m8 = a57 + a68;
+  R m6 = d57 - d68, m7 = d57 + d68;
+  R m1 = (f[1] - f[3]) + m6, m2 = (f[2] - f[4]) + m7;
+  R m3 = (f[1] + f[3]) + m8, m4 = (f[2] + f[4]) + m8;
+  const R third = R(1) / R(3), ninth = R(1) / R(9);
+  const R Xux = X * ux, Xuy = X * uy, X3 = X * third;
+  // m* = m - S (m - m_eq) + (I - S/2) m_F, with
+  // m_eq = (X, X ux, X uy, X/3, X/3, 0, X ux/3, X uy/3, X/9),
+  // m_F  = (0, Vx/3, Vy/3, 0, 0, 0, Vx/9, Vy/9, 0).
+  const R h1 = R(1) - R(0.5) * s1, h3 = R(1) - R(0.5) * s3;
+  m1 = m1 - s1 * (m1 - Xux) + h1 * (Vx * third);
+  m2 = m2 - s1 * (m2 - Xuy) + h1 * (Vy * third);
+  m3 = m3 - s2 * (m3 - X3);
+  m4 = m4 - s2 * (m4 - X3);
+  m5 = m5 - s2 * m5;
+  m6 = m6 - s3 * (m6 - Xux * third) + h3 * (Vx * ninth);
+  m7 = m7 - s3 * (m7 - Xuy * third) + h3 * (Vy * ninth);
+  m8 = m8 - s4 * (m8 - X * ninth);
+  // f = M^-1 m (m0 = X is conserved)
+  f[0] = X - m3 - m4 + m8;
+  f[1] = R(0.5) * (m1 + m3 - m6 - m8);
+  f[2] = R(0.5) * (m2 + m4 - m7 - m8);
+  f[3] = R(0.5) * (-m1 + m3 + m6 - m8);
+  f[4] = R(0.5) * (-m2 + m4 + m7 - m8);
+  f[5] = R(0.25) * (m5 + m6 + m7 + m8);
+  f[6] = R(0.25) * (-m5 - m6 + m7 + m8);
+  f[7] = R(0.25) * (m5 - m6 - m7 + m8);
+  f[8] = R(0.25) * (-m5 + m6 - m7 + m8);
+}
+
+// MRT collision of the flow LB (Eq. (29)) on h_1..h_8 (h[k] = h_{k+1}),
+// with the equilibrium (30) and source (30)-(31) in moment form:
+//   m_eq = (., rho ux, rho uy, P + Ax ux, P + Ay uy, (Ax uy + Ay ux)/2,
+//           rho ux/3, rho uy/3, P/3 + A.u/3),  A = rho u - S,
+//   m_H  = (B, Fx, Fy, B/3 + m2xx, B/3 + m2yy, m2xy, Fx/3, Fy/3,
+//           B/9 + tr m2/3),  B = u.grad rho,
+//   m2 = d_t(rho uu - (Su+uS)/2) + c_s^2 (u grad rho + grad rho u).
+// The first moments become m1 + F whatever s1 is, since rho u = m1 + F/2.
+template <class R>
+__device__ __forceinline__ void collide_flow(R* h, const Front<R>& s, R s3, R s4) {
+  const R a57 = h[4] + h[6], a68 = h[5] + h[7];
+  const R d57 = h[4] - h[6], d68 = h[5] - h[7];
+  R m5 = a57 - a68, m8 = a57 + a68;
+  R m6 = d57 - d68, m7 = d57 + d68;
+  R m1 = (h[0] - h[2]) + m6, m2 = (h[1] - h[3]) + m7;
+  R m3 = (h[0] + h[2]) + m8, m4 = (h[1] + h[3]) + m8;
+  const R third = R(1) / R(3), ninth = R(1) / R(9);
+  const R ux = s.ux, uy = s.uy;
+  const R Ax = s.jx - s.Sx, Ay = s.jy - s.Sy;
+  const R Au = Ax * ux + Ay * uy;
+  const R B = ux * s.grx + uy * s.gry;
+  const R mxx = s.dTxx + R(2) * third * ux * s.grx;
+  const R myy = s.dTyy + R(2) * third * uy * s.gry;
+  const R mxy = s.dTxy + third * (ux * s.gry + uy * s.grx);
+  const R s2 = s.s2h, h2 = R(1) - R(0.5) * s2;
+  const R h3 = R(1) - R(0.5) * s3, h4 = R(1) - R(0.5) * s4;
+  m1 = m1 + s.Fx;
+  m2 = m2 + s.Fy;
+  m3 = m3 - s2 * (m3 - (s.P + Ax * ux)) + h2 * (B * third + mxx);
+  m4 = m4 - s2 * (m4 - (s.P + Ay * uy)) + h2 * (B * third + myy);
+  m5 = m5 - s2 * (m5 - R(0.5) * (Ax * uy + Ay * ux)) + h2 * mxy;
+  m6 = m6 - s3 * (m6 - s.jx * third) + h3 * (s.Fx * third);
+  m7 = m7 - s3 * (m7 - s.jy * third) + h3 * (s.Fy * third);
+  m8 = m8 - s4 * (m8 - third * (s.P + Au)) + h4 * (B * ninth + third * (mxx + myy));
+  h[0] = R(0.5) * (m1 + m3 - m6 - m8);
+  h[1] = R(0.5) * (m2 + m4 - m7 - m8);
+  h[2] = R(0.5) * (-m1 + m3 + m6 - m8);
+  h[3] = R(0.5) * (-m2 + m4 + m7 - m8);
+  h[4] = R(0.25) * (m5 + m6 + m7 + m8);
+  h[5] = R(0.25) * (-m5 - m6 + m7 + m8);
+  h[6] = R(0.25) * (m5 - m6 - m7 + m8);
+  h[7] = R(0.25) * (-m5 + m6 - m7 + m8);
+}
+
+// The three collisions of one site.  f, g: 9 populations; h: h_1..h_8.
+template <class R, bool GENR>
+__device__ __forceinline__ void collide_site(const Phys<R>& p, const Front<R>& s,
+                                             R* f, R* g, R* h) {
+  // phase field: V = 3 d_t(phi u) + delta n  (Eq. (22))
+  collide_cde(f, s.phi, s.ux, s.uy, R(3) * s.dpux + s.delta * s.nx,
+              R(3) * s.dpuy + s.delta * s.ny, p.s1f, p.s2f, p.s3f, p.s4f);
+  // surfactant: V = 3 d_t(psi u) + j, j = r a psi n - (r-1)(n.grad psi) n;
+  // at r = 1, j = a psi n exactly as in Eq. (26)
+  R jx, jy;
+  if (GENR) {
+    const R ndg = s.nx * s.gpx + s.ny * s.gpy;
+    const R k = p.r * s.a * s.psi - p.rm1 * ndg;
+    jx = k * s.nx;
+    jy = k * s.ny;
+  } else {
+    const R k = s.a * s.psi;
+    jx = k * s.nx;
+    jy = k * s.ny;
+  }
+  collide_cde(g, s.psi, s.ux, s.uy, R(3) * s.dqux + jx, R(3) * s.dquy + jy,
+              p.s1g, p.s2g, p.s3g, p.s4g);
+  collide_flow(h, s, p.s3h, p.s4h);
+}
+
+}  // namespace lbm

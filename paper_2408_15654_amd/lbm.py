@@ -1,0 +1,220 @@
+"""Thin Python binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every step of the method runs in the HIP library ``liblbm.so``; PyTorch is
+used only to allocate the device workspace and to supply the HIP stream.
+There is no CPU fallback: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2}
+EOS = {"linear": 0, "langmuir": 1}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class NonFiniteError(LbmError):
+    pass
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("walls_y", ctypes.c_int32), ("eos", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("u_wall_bot", ctypes.c_double), ("u_wall_top", ctypes.c_double),
+        ("phiA", ctypes.c_double), ("phiB", ctypes.c_double),
+        ("W", ctypes.c_double), ("M", ctypes.c_double), ("D", ctypes.c_double),
+        ("r", ctypes.c_double), ("rhoA", ctypes.c_double), ("rhoB", ctypes.c_double),
+        ("muA", ctypes.c_double), ("muB", ctypes.c_double),
+        ("sigma0", ctypes.c_double), ("beta", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("s_free", (ctypes.c_double * 3) * 3),
+        ("fp16_scale", ctypes.c_double * 3),
+    ]
+
+
+class lbm_moments_t(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("sum_phi", ctypes.c_double),
+                ("sum_psi", ctypes.c_double), ("mom_x", ctypes.c_double),
+                ("mom_y", ctypes.c_double), ("kinetic", ctypes.c_double),
+                ("max_u", ctypes.c_double), ("nonfinite", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+EXPORTS = ("lbm_workspace_bytes", "lbm_create", "lbm_init_fields", "lbm_step",
+           "lbm_read_fields", "lbm_moments", "lbm_state_bytes", "lbm_get_state",
+           "lbm_set_state", "lbm_destroy", "lbm_last_error", "lbm_set_tile_rows",
+           "lbm_step_kernel_name")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblbm.so and declare the signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2408_15654_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER(lbm_params)
+    vp, dp, H = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p
+    lib.lbm_workspace_bytes.argtypes = [P]
+    lib.lbm_workspace_bytes.restype = ctypes.c_size_t
+    lib.lbm_create.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(H)]
+    lib.lbm_init_fields.argtypes = [H, dp, dp, dp, dp]
+    lib.lbm_step.argtypes = [H, ctypes.c_int64]
+    lib.lbm_read_fields.argtypes = [H, dp, dp, dp, dp, dp]
+    lib.lbm_moments.argtypes = [H, ctypes.POINTER(lbm_moments_t)]
+    lib.lbm_state_bytes.argtypes = [H]
+    lib.lbm_state_bytes.restype = ctypes.c_size_t
+    lib.lbm_get_state.argtypes = [H, vp, ctypes.c_size_t]
+    lib.lbm_set_state.argtypes = [H, vp, ctypes.c_size_t]
+    lib.lbm_destroy.argtypes = [H]
+    lib.lbm_destroy.restype = None
+    lib.lbm_last_error.argtypes = [H]
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    lib.lbm_set_tile_rows.argtypes = [H, ctypes.c_int32]
+    lib.lbm_step_kernel_name.argtypes = [H]
+    lib.lbm_step_kernel_name.restype = ctypes.c_char_p
+    for name in ("lbm_create", "lbm_init_fields", "lbm_step", "lbm_read_fields",
+                 "lbm_moments", "lbm_get_state", "lbm_set_state", "lbm_set_tile_rows"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def to_c_params(p: dict) -> lbm_params:
+    c = lbm_params()
+    c.nx, c.ny = int(p["nx"]), int(p["ny"])
+    c.walls_y = int(bool(p.get("walls_y", 0)))
+    c.eos = EOS[p.get("eos", "linear")] if isinstance(p.get("eos", "linear"), str) else int(p["eos"])
+    prec = p.get("precision", "fp64")
+    c.precision = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    c.reserved = 0
+    c.u_wall_bot = float(p.get("u_wall_bot", 0.0))
+    c.u_wall_top = float(p.get("u_wall_top", 0.0))
+    c.phiA = float(p.get("phiA", 1.0))
+    c.phiB = float(p.get("phiB", 0.0))
+    for k in ("W", "M", "D", "r", "rhoA", "rhoB", "muA", "muB", "sigma0", "beta"):
+        setattr(c, k, float(p[k]))
+    c.gx = float(p.get("gx", 0.0))
+    c.gy = float(p.get("gy", 0.0))
+    sf = np.asarray(p.get("s_free", np.ones((3, 3))), dtype=np.float64).reshape(3, 3)
+    for a in range(3):
+        for b in range(3):
+            c.s_free[a][b] = float(sf[a, b])
+    fs = p.get("fp16_scale", (0.0, 0.0, 0.0))
+    for a in range(3):
+        c.fp16_scale[a] = float(fs[a])
+    return c
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Simulation:
+    """One simulation on one GPU: workspace, handle and stream."""
+
+    def __init__(self, params: dict, device: str = "cuda:0", stream=None):
+        import torch
+
+        self.lib = load()
+        self.params = dict(params)
+        self._c = to_c_params(params)
+        self.nx, self.ny = self._c.nx, self._c.ny
+        nbytes = self.lib.lbm_workspace_bytes(ctypes.byref(self._c))
+        if nbytes == 0:
+            self._handle = None
+            raise LbmError(LBM_EINVAL, "invalid parameters")
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._handle = ctypes.c_void_p()
+        st = self.lib.lbm_create(ctypes.byref(self._c), ctypes.c_void_p(self.workspace.data_ptr()),
+                                 nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(self._handle))
+        if st != LBM_OK:
+            msg = self.lib.lbm_last_error(None).decode()
+            self._handle = None
+            raise LbmError(st, msg)
+
+    # --------------------------------------------------------------- api
+    def _check(self, st: int):
+        if st == LBM_OK:
+            return
+        msg = self.lib.lbm_last_error(self._handle).decode()
+        if st == LBM_ENONFINITE:
+            raise NonFiniteError(st, msg)
+        raise LbmError(st, msg)
+
+    def _field(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.size != self.nx * self.ny:
+            raise ValueError("field has the wrong size")
+        return a
+
+    def init_fields(self, phi, psi, ux, uy):
+        arrs = [self._field(a) for a in (phi, psi, ux, uy)]
+        self._check(self.lib.lbm_init_fields(self._handle, *[_dptr(a) for a in arrs]))
+
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm_step(self._handle, int(n)))
+
+    def read_fields(self) -> dict:
+        out = {k: np.empty((self.ny, self.nx)) for k in ("phi", "psi", "ux", "uy", "P")}
+        self._check(self.lib.lbm_read_fields(self._handle, *[_dptr(out[k]) for k in
+                                                            ("phi", "psi", "ux", "uy", "P")]))
+        return out
+
+    def moments(self) -> dict:
+        m = lbm_moments_t()
+        self._check(self.lib.lbm_moments(self._handle, ctypes.byref(m)))
+        return {k: getattr(m, k) for k, _ in lbm_moments_t._fields_ if k != "pad"}
+
+    def state_bytes(self) -> int:
+        return int(self.lib.lbm_state_bytes(self._handle))
+
+    def get_state(self) -> bytes:
+        buf = ctypes.create_string_buffer(self.state_bytes())
+        self._check(self.lib.lbm_get_state(self._handle, buf, len(buf)))
+        return buf.raw
+
+    def set_state(self, data: bytes):
+        buf = ctypes.create_string_buffer(data, len(data))
+        self._check(self.lib.lbm_set_state(self._handle, buf, len(data)))
+
+    def set_tile_rows(self, rows: int):
+        self._check(self.lib.lbm_set_tile_rows(self._handle, int(rows)))
+
+    def step_kernel_name(self) -> str:
+        return self.lib.lbm_step_kernel_name(self._handle).decode()
+
+    def close(self):
+        if getattr(self, "_handle", None):
+            self.lib.lbm_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
