@@ -33,7 +33,13 @@
  *     lap X = sum 2 w_i (X(x+c_i)-X(x))/cs2; next to a wall the missing
  *     neighbour row is the wall row itself (mirror ghost).
  *   - Time derivatives: backward difference X(t) - X(t-1).
- *   - n = grad phi / (|grad phi| + 1e-12).
+ *   - n = grad phi / (|grad phi| + eps), eps = 1e-4 (phiA - phiB) / W, i.e.
+ *     1e-4 of the largest gradient of the profile (7).  Inside a drop,
+ *     far from its rim, |grad phi| can fall below delta(phi) (at the centre
+ *     it cancels to rounding level); there the sharpening flux with a unit
+ *     normal would be anti-diffusive and the step would amplify rounding
+ *     differences without bound.  With this eps the bulk stays diffusive,
+ *     while at the interface (|grad phi| ~ 1/W) n is a unit vector to 1e-4.
  *   - General r: the source of the psi-LB carries
  *       j = r a psi n - (r-1) (n . grad psi) n,  a = 4(phiA+phiB-2phi)/(W dphi),
  *     from Eqs. (3)-(4) with psi = delta psi_hat and grad delta / delta = a n;
@@ -131,6 +137,11 @@ static int check_params(const or_params *p) {
 }
 
 /* ---------------------------------------------------------------- EOS etc. */
+
+/* Regularisation of the unit normal n = grad phi / (|grad phi| + eps). */
+static double normal_eps(const or_params *p) {
+  return 1e-4 * (p->phiA - p->phiB) / p->W;
+}
 
 /* Eq. (15). */
 static double rho_of(const or_params *p, double phi) {
@@ -377,7 +388,8 @@ static void front_half(const or_params *p, const double *fs, const double *gs,
       grad(p, fr->psi, x, y, &gqx, &gqy);
       double lp = lap(p, fr->phi, x, y);
       double gn = sqrt(gpx * gpx + gpy * gpy);
-      double nx_ = gpx / (gn + 1e-12), ny_ = gpy / (gn + 1e-12);
+      double eps = normal_eps(p);
+      double nx_ = gpx / (gn + eps), ny_ = gpy / (gn + eps);
       double delta = 4.0 * (p->phiA - phi) * (phi - p->phiB) / (p->W * dphi);
       double a = 4.0 * (p->phiA + p->phiB - 2.0 * phi) / (p->W * dphi);
       double rho = rho_of(p, phi);
@@ -478,7 +490,8 @@ int or_init(const or_params *p, const double *phi0, const double *psi0,
       double gpx, gpy;
       grad(p, phi0, x, y, &gpx, &gpy);
       double gn = sqrt(gpx * gpx + gpy * gpy);
-      double nx_ = gpx / (gn + 1e-12), ny_ = gpy / (gn + 1e-12);
+      double eps = normal_eps(p);
+      double nx_ = gpx / (gn + eps), ny_ = gpy / (gn + eps);
       double delta = 4.0 * (p->phiA - phi) * (phi - p->phiB) / (p->W * dphi);
       or_site s;
       memset(&s, 0, sizeof s);

@@ -343,7 +343,7 @@ lbm_init_kernel(const SiteArgs a, const Phys<double> p, S *__restrict__ dst) {
   grad9(v, gx, gy);
   const double phi = phi0[k], psi = psi0[k], ux = ux0[k], uy = uy0[k];
   const double gn = sqrt(gx * gx + gy * gy);
-  const double inv = 1.0 / (gn + 1e-12);
+  const double inv = 1.0 / (gn + p.eps_n);
   const double delta = p.c4W * ((p.phiA - phi) * (phi - p.phiB));
   const double Sx = p.Mdrho * (gx - delta * gx * inv);
   const double Sy = p.Mdrho * (gy - delta * gy * inv);
@@ -595,6 +595,10 @@ Phys<R> make_phys(const lbm_params &q) {
   p.uwb = R(q.u_wall_bot);
   p.uwt = R(q.u_wall_top);
   p.psi_max = R(1.0 - 1e-9);
+  // 1e-4 of the largest gradient of the equilibrium profile: inside drops,
+  // where |grad phi| can fall below delta(phi), the sharpening flux must not
+  // become anti-diffusive (it would amplify rounding differences)
+  p.eps_n = R(1e-4 * dphi / q.W);
   p.eos = q.eos;
   return p;
 }

@@ -35,6 +35,7 @@ struct Phys {
   R s3h, s4h;              // free rates of the flow LB (s2 is per site)
   R uwb, uwt;              // wall speeds (bottom, top)
   R psi_max;               // Langmuir clamp 1 - 1e-9
+  R eps_n;                 // n = grad phi / (|grad phi| + eps_n)
   int eos;                 // 0 linear, 1 Langmuir
 };
 
@@ -106,7 +107,7 @@ __device__ __forceinline__ void site_front(const Phys<R>& p, Front<R>& s, R phi,
   s.psi = psi;
   const R gn2 = gfx * gfx + gfy * gfy;
   const R gn = sqrt(gn2);
-  const R inv = R(1) / (gn + R(1e-12));
+  const R inv = R(1) / (gn + p.eps_n);
   s.nx = gfx * inv;
   s.ny = gfy * inv;
   const R qa = p.phiA - phi, qb = phi - p.phiB, qab = p.phiAB - phi - phi;
