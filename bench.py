@@ -23,7 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak (AMD spec)
-STORE_BYTES = {"fp64": 8, "fp32": 4}
+STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16dev": 2}
+FIELD_BYTES = {"fp64": 8, "fp32": 4, "fp16dev": 4}
 KERNEL_SOURCES = ("paper_2408_15654_amd/csrc/lbm.hip", "paper_2408_15654_amd/csrc/lbm_device.h")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "lbm_step_kernel_many_drops_2048_counters.json")
 
@@ -32,9 +33,8 @@ def algorithmic_bytes_per_site(precision: str, has_s: bool) -> int:
     """Bytes one site-update must move: 26 live populations read and written
     (f_0..f_8, g_0..g_8, h_1..h_8) plus the previous level (phi, psi, ux,
     uy and, with a density contrast, Sx, Sy) read and written."""
-    b = STORE_BYTES[precision]
     aux = 6 if has_s else 4
-    return 2 * 26 * b + 2 * aux * b
+    return 2 * 26 * STORE_BYTES[precision] + 2 * aux * FIELD_BYTES[precision]
 
 
 def kernel_source_hash() -> str:
@@ -106,7 +106,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp16dev"])
     ap.add_argument("--rows", type=int, default=0, help="tile height override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")

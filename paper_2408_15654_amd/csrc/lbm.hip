@@ -2,24 +2,30 @@
 // (phase field f, surfactant g, flow h; arXiv:2408.15654), for gfx950.
 //
 // State on the device (structure of arrays, x fastest, one plane per
-// population, planes padded to 64 elements):
-//   populations  planes 0-8 f_0..f_8, 9-17 g_0..g_8, 18-25 h_1..h_8 (h_0 is
-//                never read, see lbm_device.h), post-collision values of the
-//                previous step, two copies (ping-pong);
-//   aux          planes phi, psi, ux, uy, Sx, Sy of the previous time level
-//                (the first-order time differences need them), updated in
-//                place: every site reads and writes only its own entries;
+// quantity, planes padded to 64 elements), two copies (ping-pong):
+//   populations  planes 0-8: deviations d_i = f_i - w_i phi of the
+//                post-collision phase-field populations from the rest
+//                equilibrium of their own site; 9-17: the same for g with
+//                psi; 18-25: h_1..h_8 (h_0 is never read: column 0 of M is
+//                e_0 and rows 1-8 of M^-1 start with 0);
+//   rest         planes phi, psi of the same (previous) time level.
+// plus, updated in place (each site reads and writes only its own entries):
+//   aux          planes ux, uy, Sx, Sy of the previous time level (the
+//                first-order time differences need them; phi, psi come from
+//                the rest planes);
 //   scratch      float64 planes for host transfers and read-back.
+// Storage type: float64, float32, or float16 with per-field power-of-two
+// scales (deviations and h are small numbers; phi, psi stay float32).
 //
 // One time step is ONE launch of lbm_step_kernel.  Each wavefront owns a
-// strip of 62 columns (plus one halo column on each side, lanes 0 and 63)
-// and walks down a tile of rows.  For each row it pulls the f and g
-// populations of the NEXT row (so their zeroth moments phi, psi and
-// sigma(psi) are known one row ahead), keeps a three-row window of phi,
-// psi, sigma in registers, takes the x-neighbours from adjacent lanes with
-// cross-lane moves, and so evaluates the 9-point stencils without LDS or
-// barriers.  The h populations and the previous level are read for the
-// current row only, and the 26 post-collision populations are written once.
+// strip of 62 columns (plus one halo column on each side, lanes 0 and
+// w+1) and walks down a tile of rows.  For each row it pulls the f and g
+// deviations of the NEXT row, rebuilds that row's phi, psi (and sigma(psi))
+// from them and the rest values of their source sites, keeps a three-row
+// window of phi, psi, sigma in registers and takes x-neighbours from
+// adjacent lanes with cross-lane moves, so the 9-point stencils need no LDS
+// and no barrier.  The h populations and the previous level are read for
+// the current row only, and every population is written once.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -40,21 +46,67 @@ constexpr int kWave = 64;
 constexpr int kStrip = kWave - 2;  // interior columns per wavefront
 constexpr int kWavesPerBlock = 4;
 constexpr int kPlanes = 26;
-constexpr int kAux = 6;
+constexpr int kRest = 2;
+constexpr int kAux = 4;
 constexpr int kScratch = 8;
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceVals = 8;
 
-// D2Q9 tables for the per-site (non-sliding) kernels.
-__constant__ int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__constant__ int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+// Storage precisions: S population type, A type of phi/psi/u/S planes,
+// R arithmetic type, SCALED: populations carry power-of-two scales.
+struct F64 {
+  using S = double;
+  using A = double;
+  using R = double;
+  static constexpr bool SCALED = false;
+};
+struct F32 {
+  using S = float;
+  using A = float;
+  using R = float;
+  static constexpr bool SCALED = false;
+};
+struct F16 {
+  using S = _Float16;
+  using A = float;
+  using R = float;
+  static constexpr bool SCALED = true;
+};
 
-template <class R>
+template <class P>
+struct Scales {
+  typename P::R f, g, h;     // multiply before storing
+  typename P::R fi, gi, hi;  // multiply after loading
+};
+
+template <class P>
+__device__ __forceinline__ typename P::R ld(const typename P::S *p, long long i,
+                                            typename P::R inv) {
+  using R = typename P::R;
+  if constexpr (P::SCALED)
+    return R(p[i]) * inv;
+  else
+    return R(p[i]);
+}
+template <class P>
+__device__ __forceinline__ void st(typename P::S *p, long long i, typename P::R v,
+                                   typename P::R scale) {
+  using S = typename P::S;
+  if constexpr (P::SCALED)
+    p[i] = S(v * scale);
+  else
+    p[i] = S(v);
+}
+
+template <class P>
 struct StepArgs {
-  Phys<R> p;
-  const void *src;
-  void *dst;
-  void *aux;
+  Phys<typename P::R> p;
+  Scales<P> sc;
+  const typename P::S *src;
+  const typename P::A *src_rest;
+  typename P::S *dst;
+  typename P::A *dst_rest;
+  typename P::A *aux;
   int *flag;
   long long plane;
   int nx, ny, walls;
@@ -80,46 +132,70 @@ __device__ __forceinline__ RowIdx row_index(int y, int nx, int ny, int walls) {
   return r;
 }
 
+// Row y of the lattice for a row index that may lie one or two rows
+// outside: periodic wrap, or clamped between walls (clamped rows are only
+// read where the bounce-back makes their value irrelevant).
+__device__ __forceinline__ int wrap_row(int y, int ny, int walls) {
+  if (walls) return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+  return y < 0 ? y + ny : (y >= ny ? y - ny : y);
+}
+
 // Pull streaming of one 9-population field to site (x, row): population i
 // comes from x - c_i; across a wall it is the opposite population of the
 // site itself (half-way bounce-back, no flux).
-template <class S, class R>
-__device__ __forceinline__ void pull9(const S *__restrict__ s, long long pl,
+template <class P>
+__device__ __forceinline__ void pull9(const typename P::S *__restrict__ s, long long pl,
                                       const RowIdx &r, int x, int xm, int xp,
-                                      R *f) {
-  f[0] = R(s[r.rc + x]);
-  f[1] = R(s[pl + r.rc + xm]);
-  f[2] = R(r.bot ? s[4 * pl + r.rc + x] : s[2 * pl + r.rm + x]);
-  f[3] = R(s[3 * pl + r.rc + xp]);
-  f[4] = R(r.top ? s[2 * pl + r.rc + x] : s[4 * pl + r.rp + x]);
-  f[5] = R(r.bot ? s[7 * pl + r.rc + x] : s[5 * pl + r.rm + xm]);
-  f[6] = R(r.bot ? s[8 * pl + r.rc + x] : s[6 * pl + r.rm + xp]);
-  f[7] = R(r.top ? s[5 * pl + r.rc + x] : s[7 * pl + r.rp + xp]);
-  f[8] = R(r.top ? s[6 * pl + r.rc + x] : s[8 * pl + r.rp + xm]);
+                                      typename P::R inv, typename P::R *f) {
+  f[0] = ld<P>(s, r.rc + x, inv);
+  f[1] = ld<P>(s, pl + r.rc + xm, inv);
+  f[2] = r.bot ? ld<P>(s, 4 * pl + r.rc + x, inv) : ld<P>(s, 2 * pl + r.rm + x, inv);
+  f[3] = ld<P>(s, 3 * pl + r.rc + xp, inv);
+  f[4] = r.top ? ld<P>(s, 2 * pl + r.rc + x, inv) : ld<P>(s, 4 * pl + r.rp + x, inv);
+  f[5] = r.bot ? ld<P>(s, 7 * pl + r.rc + x, inv) : ld<P>(s, 5 * pl + r.rm + xm, inv);
+  f[6] = r.bot ? ld<P>(s, 8 * pl + r.rc + x, inv) : ld<P>(s, 6 * pl + r.rm + xp, inv);
+  f[7] = r.top ? ld<P>(s, 5 * pl + r.rc + x, inv) : ld<P>(s, 7 * pl + r.rp + xp, inv);
+  f[8] = r.top ? ld<P>(s, 6 * pl + r.rc + x, inv) : ld<P>(s, 8 * pl + r.rp + xm, inv);
 }
 
 // Pull of h_1..h_8 (planes 18-25); across a wall, bounce-back with Ladd's
 // moving-wall term 2 w_i rho_w (c_i.u_w)/c_s^2 = rho_w c_ix u_w / 6 for the
 // diagonal populations (rho_w = rho at the site at collision time).
-template <class S, class R>
-__device__ __forceinline__ void pull_h(const S *__restrict__ s0, long long pl,
+template <class P>
+__device__ __forceinline__ void pull_h(const typename P::S *__restrict__ s0, long long pl,
                                        const RowIdx &r, int x, int xm, int xp,
-                                       R rho_w, R uwb, R uwt, R *h) {
-  const S *s = s0 + 18 * pl;  // s[(i-1) pl] is h_i
+                                       typename P::R inv, typename P::R rho_w,
+                                       typename P::R uwb, typename P::R uwt,
+                                       typename P::R *h) {
+  using R = typename P::R;
+  const typename P::S *s = s0 + 18 * pl;  // s[(i-1) pl] is h_i
   const R kb = rho_w * uwb * R(1.0 / 6.0), kt = rho_w * uwt * R(1.0 / 6.0);
-  h[0] = R(s[r.rc + xm]);
-  h[1] = R(r.bot ? s[3 * pl + r.rc + x] : s[pl + r.rm + x]);
-  h[2] = R(s[2 * pl + r.rc + xp]);
-  h[3] = R(r.top ? s[pl + r.rc + x] : s[3 * pl + r.rp + x]);
-  h[4] = r.bot ? R(s[6 * pl + r.rc + x]) + kb : R(s[4 * pl + r.rm + xm]);
-  h[5] = r.bot ? R(s[7 * pl + r.rc + x]) - kb : R(s[5 * pl + r.rm + xp]);
-  h[6] = r.top ? R(s[4 * pl + r.rc + x]) - kt : R(s[6 * pl + r.rp + xp]);
-  h[7] = r.top ? R(s[5 * pl + r.rc + x]) + kt : R(s[7 * pl + r.rp + xm]);
+  h[0] = ld<P>(s, r.rc + xm, inv);
+  h[1] = r.bot ? ld<P>(s, 3 * pl + r.rc + x, inv) : ld<P>(s, pl + r.rm + x, inv);
+  h[2] = ld<P>(s, 2 * pl + r.rc + xp, inv);
+  h[3] = r.top ? ld<P>(s, pl + r.rc + x, inv) : ld<P>(s, 3 * pl + r.rp + x, inv);
+  h[4] = r.bot ? ld<P>(s, 6 * pl + r.rc + x, inv) + kb : ld<P>(s, 4 * pl + r.rm + xm, inv);
+  h[5] = r.bot ? ld<P>(s, 7 * pl + r.rc + x, inv) - kb : ld<P>(s, 5 * pl + r.rm + xp, inv);
+  h[6] = r.top ? ld<P>(s, 4 * pl + r.rc + x, inv) - kt : ld<P>(s, 6 * pl + r.rp + xp, inv);
+  h[7] = r.top ? ld<P>(s, 5 * pl + r.rc + x, inv) + kt : ld<P>(s, 7 * pl + r.rp + xm, inv);
 }
 
+// Rest values of the nine source sites of a row r relative to the site's
+// own value: e_i = X(x - c_i) - X(x); bounced populations come from the
+// site itself (e_i = 0).  v holds X at rows r-1 (m), r (c), r+1 (n) of
+// columns x-1 (L), x, x+1 (R).
 template <class R>
-__device__ __forceinline__ R sum9(const R *f) {
-  return ((f[0] + (f[1] + f[2])) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
+__device__ __forceinline__ void source_offsets(const Nine<R> &v, bool bot, bool top, R *e) {
+  const R c = v.c;
+  e[0] = R(0);
+  e[1] = v.cL - c;
+  e[3] = v.cR - c;
+  e[2] = bot ? R(0) : v.m - c;
+  e[5] = bot ? R(0) : v.mL - c;
+  e[6] = bot ? R(0) : v.mR - c;
+  e[4] = top ? R(0) : v.n - c;
+  e[7] = top ? R(0) : v.nR - c;
+  e[8] = top ? R(0) : v.nL - c;
 }
 
 // Value of lane-1 / lane+1 of the wavefront.
@@ -147,15 +223,53 @@ __device__ __forceinline__ Nine<R> window(R m, R c, R n) {
   return v;
 }
 
+// One column of an old rest field with its two x-neighbours.  The halo
+// lanes (0 and w+1) have no lane beyond them and read that neighbour.
+template <class R>
+struct Col3 {
+  R L, C, Rt;
+};
+
+template <class A, class R>
+__device__ __forceinline__ Col3<R> load_col3(const A *__restrict__ a, long long row,
+                                             int x, int xm, int xp, int lane, int w) {
+  Col3<R> c;
+  c.C = R(a[row + x]);
+  c.L = from_left(c.C);
+  c.Rt = from_right(c.C);
+  if (lane == 0) c.L = R(a[row + xm]);
+  if (lane == w + 1) c.Rt = R(a[row + xp]);
+  return c;
+}
+
+template <class R>
+__device__ __forceinline__ Nine<R> nine_of(const Col3<R> &m, const Col3<R> &c,
+                                           const Col3<R> &n) {
+  Nine<R> v;
+  v.mL = m.L;
+  v.m = m.C;
+  v.mR = m.Rt;
+  v.cL = c.L;
+  v.c = c.C;
+  v.cR = c.Rt;
+  v.nL = n.L;
+  v.n = n.C;
+  v.nR = n.Rt;
+  return v;
+}
+
 // The fused step: pull-stream + boundaries, phi/psi/sigma, stencils, forces,
 // closures, three MRT collisions, store.  See the file header.
-template <class S, class R, bool GENR, bool HAS_S>
+template <class P, bool GENR, bool HAS_S>
 __global__ void __launch_bounds__(256)
-lbm_step_kernel(const StepArgs<R> a) {
+lbm_step_kernel(const StepArgs<P> a) {
+  using R = typename P::R;
+  using S = typename P::S;
+  using A = typename P::A;
   const int lane = threadIdx.x & (kWave - 1);
   const int tile = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (tile >= a.ntiles) return;  // whole wavefronts only
-  const int nx = a.nx, ny = a.ny;
+  const int nx = a.nx, ny = a.ny, walls = a.walls;
   const int strip = tile % a.nstrips;
   const int chunk = tile / a.nstrips;
   const int x0 = strip * kStrip;
@@ -168,68 +282,78 @@ lbm_step_kernel(const StepArgs<R> a) {
   const int y0 = chunk * a.rows;
   const int y1 = min(y0 + a.rows, ny);
   const long long pl = a.plane;
-  const S *__restrict__ src = static_cast<const S *>(a.src);
-  S *__restrict__ dst = static_cast<S *>(a.dst);
-  S *__restrict__ aux = static_cast<S *>(a.aux);
+  const S *__restrict__ src = a.src;
+  const A *__restrict__ rX = a.src_rest;       // old phi
+  const A *__restrict__ rY = a.src_rest + pl;  // old psi
+  S *__restrict__ dst = a.dst;
+  A *__restrict__ aux = a.aux;
   const Phys<R> &p = a.p;
+  const Scales<P> &sc = a.sc;
 
-  R fc[9], gc[9];
+  // old rest field at row y (wrapped or clamped) with x-neighbours
+  auto col = [&](const A *f, int y) {
+    return load_col3<A, R>(f, (long long)wrap_row(y, ny, walls) * nx, x, xm, xp, lane, w);
+  };
+  // new phi, psi, sigma of row r and its deviations (relative to them),
+  // given the old rest fields at rows r-1, r, r+1
+  auto advance = [&](int r, const Col3<R> &Xm, const Col3<R> &Xc, const Col3<R> &Xn,
+                     const Col3<R> &Ym, const Col3<R> &Yc, const Col3<R> &Yn, R *d,
+                     R *q, R &ph, R &ps, R &sg) {
+    const RowIdx ri = row_index(r, nx, ny, walls);
+    pull9<P>(src, pl, ri, x, xm, xp, sc.fi, d);
+    pull9<P>(src + 9 * pl, pl, ri, x, xm, xp, sc.gi, q);
+    R e[9];
+    source_offsets(nine_of(Xm, Xc, Xn), ri.bot, ri.top, e);
+    ph = restream(d, e, Xc.C);
+    source_offsets(nine_of(Ym, Yc, Yn), ri.bot, ri.top, e);
+    ps = restream(q, e, Yc.C);
+    sg = sigma_of(p, ps);
+  };
+
+  Col3<R> X0 = col(rX, y0 - 1), X1 = col(rX, y0), X2 = col(rX, y0 + 1);
+  Col3<R> Y0 = col(rY, y0 - 1), Y1 = col(rY, y0), Y2 = col(rY, y0 + 1);
+  R dc[9], qc[9];
   R phc, psc, sgc, phm, psm, sgm;
-  {
-    RowIdx r = row_index(y0, nx, ny, a.walls);
-    pull9(src, pl, r, x, xm, xp, fc);
-    pull9(src + 9 * pl, pl, r, x, xm, xp, gc);
-    phc = sum9(fc);
-    psc = sum9(gc);
-    sgc = sigma_of(p, psc);
-  }
-  if (a.walls && y0 == 0) {  // mirror ghost row below the bottom wall
+  advance(y0, X0, X1, X2, Y0, Y1, Y2, dc, qc, phc, psc, sgc);
+  if (walls && y0 == 0) {  // mirror ghost row below the bottom wall
     phm = phc;
     psm = psc;
     sgm = sgc;
   } else {
-    R ft[9], gt[9];
-    const int ym = y0 == 0 ? ny - 1 : y0 - 1;
-    RowIdx r = row_index(ym, nx, ny, a.walls);
-    pull9(src, pl, r, x, xm, xp, ft);
-    pull9(src + 9 * pl, pl, r, x, xm, xp, gt);
-    phm = sum9(ft);
-    psm = sum9(gt);
-    sgm = sigma_of(p, psm);
+    R dt[9], qt[9];
+    const Col3<R> Xa = col(rX, y0 - 2), Ya = col(rY, y0 - 2);
+    advance(y0 == 0 ? ny - 1 : y0 - 1, Xa, X0, X1, Ya, Y0, Y1, dt, qt, phm, psm, sgm);
   }
+  // window of old rest values: rows y-1 (X0), y (X1), y+1 (X2)
 
   for (int y = y0; y < y1; ++y) {
-    // next row: its populations are kept for the next iteration
-    R fn[9], gn[9];
+    const Col3<R> X3 = col(rX, y + 2), Y3 = col(rY, y + 2);
+    // next row: its deviations are kept for the next iteration
+    R dn[9], qn[9];
     R phn, psn, sgn;
-    const bool ghost = a.walls && y + 1 == ny;
+    const bool ghost = walls && y + 1 == ny;
     if (!ghost) {
-      const int yn = y + 1 == ny ? 0 : y + 1;
-      RowIdx r = row_index(yn, nx, ny, a.walls);
-      pull9(src, pl, r, x, xm, xp, fn);
-      pull9(src + 9 * pl, pl, r, x, xm, xp, gn);
-      phn = sum9(fn);
-      psn = sum9(gn);
-      sgn = sigma_of(p, psn);
+      advance(y + 1 == ny ? 0 : y + 1, X1, X2, X3, Y1, Y2, Y3, dn, qn, phn, psn, sgn);
     } else {  // mirror ghost row above the top wall
-      for (int i = 0; i < 9; ++i) fn[i] = gn[i] = R(0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) dn[i] = qn[i] = R(0);
       phn = phc;
       psn = psc;
       sgn = sgc;
     }
 
     // current row: h populations and the previous level
-    const RowIdx r = row_index(y, nx, ny, a.walls);
+    const RowIdx r = row_index(y, nx, ny, walls);
     const long long k = r.rc + x;
-    const R php = R(aux[k]), psp = R(aux[pl + k]);
-    const R uxp = R(aux[2 * pl + k]), uyp = R(aux[3 * pl + k]);
+    const R php = X1.C, psp = Y1.C;
+    const R uxp = R(aux[k]), uyp = R(aux[pl + k]);
     R Sxp = R(0), Syp = R(0);
     if (HAS_S) {
-      Sxp = R(aux[4 * pl + k]);
-      Syp = R(aux[5 * pl + k]);
+      Sxp = R(aux[2 * pl + k]);
+      Syp = R(aux[3 * pl + k]);
     }
     R h[8];
-    pull_h(src, pl, r, x, xm, xp, rho_of(p, php), p.uwb, p.uwt, h);
+    pull_h<P>(src, pl, r, x, xm, xp, sc.hi, rho_of(p, php), p.uwb, p.uwt, h);
 
     // stencils from the register window
     const Nine<R> vphi = window(phm, phc, phn);
@@ -240,36 +364,36 @@ lbm_step_kernel(const StepArgs<R> a) {
     const R lphi = lap9(vphi);
 
     Front<R> s;
-    site_front<R, HAS_S>(p, s, phc, psc, sgc, gfx, gfy, lphi, gsx, gsy, h, php,
-                         psp, uxp, uyp, Sxp, Syp);
+    site_front<R, HAS_S>(p, s, phc, psc, sgc, gfx, gfy, lphi, gsx, gsy, h, php, psp, uxp,
+                         uyp, Sxp, Syp);
     if (GENR) {
       const Nine<R> vpsi = window(psm, psc, psn);
       grad9(vpsi, s.gpx, s.gpy);
     } else {
       s.gpx = s.gpy = R(0);
     }
-    collide_site<R, GENR>(p, s, fc, gc, h);
+    collide_site<R, GENR>(p, s, dc, qc, h);
 
     if (interior) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        dst[i * pl + k] = S(fc[i]);
-        dst[(9 + i) * pl + k] = S(gc[i]);
+        st<P>(dst, i * pl + k, dc[i], sc.f);
+        st<P>(dst, (9 + i) * pl + k, qc[i], sc.g);
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) dst[(18 + i) * pl + k] = S(h[i]);
-      aux[k] = S(phc);
-      aux[pl + k] = S(psc);
-      aux[2 * pl + k] = S(s.ux);
-      aux[3 * pl + k] = S(s.uy);
+      for (int i = 0; i < 8; ++i) st<P>(dst, (18 + i) * pl + k, h[i], sc.h);
+      a.dst_rest[k] = A(phc);
+      a.dst_rest[pl + k] = A(psc);
+      aux[k] = A(s.ux);
+      aux[pl + k] = A(s.uy);
       if (HAS_S) {
-        aux[4 * pl + k] = S(s.Sx);
-        aux[5 * pl + k] = S(s.Sy);
+        aux[2 * pl + k] = A(s.Sx);
+        aux[3 * pl + k] = A(s.Sy);
       }
       if (!isfinite(phc + psc + s.ux + s.uy)) *a.flag = 1;
     }
 
-    // slide the window
+    // slide the windows
     phm = phc;
     psm = psc;
     sgm = sgc;
@@ -278,9 +402,15 @@ lbm_step_kernel(const StepArgs<R> a) {
     sgc = sgn;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      fc[i] = fn[i];
-      gc[i] = gn[i];
+      dc[i] = dn[i];
+      qc[i] = qn[i];
     }
+    X0 = X1;
+    X1 = X2;
+    X2 = X3;
+    Y0 = Y1;
+    Y1 = Y2;
+    Y2 = Y3;
   }
 }
 
@@ -288,8 +418,8 @@ lbm_step_kernel(const StepArgs<R> a) {
 
 // Neighbour of site (x, y) at offset (dx, dy) in {-1,0,1}^2: periodic in x;
 // periodic in y or, between walls, the wall row itself (mirror ghost).
-__device__ __forceinline__ long long nbr_index(int x, int y, int dx, int dy,
-                                               int nx, int ny, int walls) {
+__device__ __forceinline__ long long nbr_index(int x, int y, int dx, int dy, int nx,
+                                               int ny, int walls) {
   int xx = x + dx, yy = y + dy;
   xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
   if (walls) {
@@ -300,26 +430,31 @@ __device__ __forceinline__ long long nbr_index(int x, int y, int dx, int dy,
   return (long long)yy * nx + xx;
 }
 
-template <class R>
-__device__ __forceinline__ Nine<R> gather9(const R *a, int x, int y, int nx,
-                                           int ny, int walls) {
+template <class T, class R>
+__device__ __forceinline__ Nine<R> gather9(const T *a, int x, int y, int nx, int ny,
+                                           int walls) {
   Nine<R> v;
-  v.mL = a[nbr_index(x, y, -1, -1, nx, ny, walls)];
-  v.m = a[nbr_index(x, y, 0, -1, nx, ny, walls)];
-  v.mR = a[nbr_index(x, y, 1, -1, nx, ny, walls)];
-  v.cL = a[nbr_index(x, y, -1, 0, nx, ny, walls)];
-  v.c = a[nbr_index(x, y, 0, 0, nx, ny, walls)];
-  v.cR = a[nbr_index(x, y, 1, 0, nx, ny, walls)];
-  v.nL = a[nbr_index(x, y, -1, 1, nx, ny, walls)];
-  v.n = a[nbr_index(x, y, 0, 1, nx, ny, walls)];
-  v.nR = a[nbr_index(x, y, 1, 1, nx, ny, walls)];
+  v.mL = R(a[nbr_index(x, y, -1, -1, nx, ny, walls)]);
+  v.m = R(a[nbr_index(x, y, 0, -1, nx, ny, walls)]);
+  v.mR = R(a[nbr_index(x, y, 1, -1, nx, ny, walls)]);
+  v.cL = R(a[nbr_index(x, y, -1, 0, nx, ny, walls)]);
+  v.c = R(a[nbr_index(x, y, 0, 0, nx, ny, walls)]);
+  v.cR = R(a[nbr_index(x, y, 1, 0, nx, ny, walls)]);
+  v.nL = R(a[nbr_index(x, y, -1, 1, nx, ny, walls)]);
+  v.n = R(a[nbr_index(x, y, 0, 1, nx, ny, walls)]);
+  v.nR = R(a[nbr_index(x, y, 1, 1, nx, ny, walls)]);
   return v;
 }
 
+template <class P>
 struct SiteArgs {
-  const void *src;
-  void *aux;
+  const typename P::S *src;
+  const typename P::A *src_rest;
+  typename P::S *dst;
+  typename P::A *dst_rest;
+  typename P::A *aux;
   double *scratch;  // kScratch float64 planes
+  Scales<P> sc;
   long long plane;
   int nx, ny, walls;
 };
@@ -327,10 +462,14 @@ struct SiteArgs {
 // Initial state in float64: post-collision populations := equilibria of
 // Eqs. (22), (26), (30) with P = 0 and S of Eq. (16) from the gradient of
 // the initial phi; previous level := the initial fields.  Inputs are
-// scratch planes 0-3 (phi, psi, ux, uy).
-template <class S>
+// scratch planes 0-3 (phi, psi, ux, uy).  f and g are stored as deviations
+// from w_i times the STORED rest value, so storing phi, psi in a narrower
+// type leaves the populations themselves exact up to their own rounding.
+template <class P>
 __global__ void __launch_bounds__(256)
-lbm_init_kernel(const SiteArgs a, const Phys<double> p, S *__restrict__ dst) {
+lbm_init_kernel(const SiteArgs<P> a, const Phys<double> p) {
+  using A = typename P::A;
+  using R = typename P::R;
   const long long n = (long long)a.nx * a.ny;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
@@ -338,7 +477,7 @@ lbm_init_kernel(const SiteArgs a, const Phys<double> p, S *__restrict__ dst) {
   const long long pl = a.plane;
   const double *phi0 = a.scratch, *psi0 = a.scratch + pl;
   const double *ux0 = a.scratch + 2 * pl, *uy0 = a.scratch + 3 * pl;
-  const Nine<double> v = gather9(phi0, x, y, a.nx, a.ny, a.walls);
+  const Nine<double> v = gather9<double, double>(phi0, x, y, a.nx, a.ny, a.walls);
   double gx, gy;
   grad9(v, gx, gy);
   const double phi = phi0[k], psi = psi0[k], ux = ux0[k], uy = uy0[k];
@@ -350,45 +489,53 @@ lbm_init_kernel(const SiteArgs a, const Phys<double> p, S *__restrict__ dst) {
   const double rho = rho_of(p, phi);
   const double jx = rho * ux, jy = rho * uy;
   const double Ax = jx - Sx, Ay = jy - Sy, Au = Ax * ux + Ay * uy;
+  const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  const double phis = double(A(phi)), psis = double(A(psi));
   for (int i = 0; i < 9; ++i) {
-    const double cu = kCx[i] * ux + kCy[i] * uy;
-    dst[i * pl + k] = S(w[i] * phi * (1.0 + 3.0 * cu));
-    dst[(9 + i) * pl + k] = S(w[i] * psi * (1.0 + 3.0 * cu));
+    const double cu = cx[i] * ux + cy[i] * uy;
+    st<P>(a.dst, i * pl + k, R(w[i] * (phi - phis) + w[i] * phi * 3.0 * cu), a.sc.f);
+    st<P>(a.dst, (9 + i) * pl + k, R(w[i] * (psi - psis) + w[i] * psi * 3.0 * cu), a.sc.g);
     if (i > 0) {
-      const double cj = kCx[i] * jx + kCy[i] * jy;
-      const double cA = kCx[i] * Ax + kCy[i] * Ay;
-      dst[(17 + i) * pl + k] = S(w[i] * (3.0 * cj + 4.5 * cA * cu - 1.5 * Au));
+      const double cj = cx[i] * jx + cy[i] * jy;
+      const double cA = cx[i] * Ax + cy[i] * Ay;
+      st<P>(a.dst, (17 + i) * pl + k, R(w[i] * (3.0 * cj + 4.5 * cA * cu - 1.5 * Au)),
+            a.sc.h);
     }
   }
-  S *aux = static_cast<S *>(a.aux);
-  aux[k] = S(phi);
-  aux[pl + k] = S(psi);
-  aux[2 * pl + k] = S(ux);
-  aux[3 * pl + k] = S(uy);
-  aux[4 * pl + k] = S(Sx);
-  aux[5 * pl + k] = S(Sy);
+  a.dst_rest[k] = A(phi);
+  a.dst_rest[pl + k] = A(psi);
+  a.aux[k] = A(ux);
+  a.aux[pl + k] = A(uy);
+  a.aux[2 * pl + k] = A(Sx);
+  a.aux[3 * pl + k] = A(Sy);
 }
 
 // Read-back, pass 1: phi, psi, sigma of the current level into scratch
-// planes 5-7 (arithmetic type R).
-template <class S, class R>
+// planes 5-7 (arithmetic type R), by the same streaming as the step.
+template <class P>
 __global__ void __launch_bounds__(256)
-lbm_macro_scalars_kernel(const SiteArgs a, const Phys<R> p) {
+lbm_macro_scalars_kernel(const SiteArgs<P> a, const Phys<typename P::R> p) {
+  using R = typename P::R;
   const long long n = (long long)a.nx * a.ny;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int x = int(k % a.nx), y = int(k / a.nx);
   const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
-  const S *src = static_cast<const S *>(a.src);
   const long long pl = a.plane;
   const RowIdx r = row_index(y, a.nx, a.ny, a.walls);
-  R f[9], g[9];
-  pull9(src, pl, r, x, xm, xp, f);
-  pull9(src + 9 * pl, pl, r, x, xm, xp, g);
+  R d[9], q[9], e[9];
+  pull9<P>(a.src, pl, r, x, xm, xp, a.sc.fi, d);
+  pull9<P>(a.src + 9 * pl, pl, r, x, xm, xp, a.sc.gi, q);
+  const Nine<R> vx = gather9<typename P::A, R>(a.src_rest, x, y, a.nx, a.ny, a.walls);
+  source_offsets(vx, r.bot, r.top, e);
+  const R phi = restream(d, e, vx.c);
+  const Nine<R> vy = gather9<typename P::A, R>(a.src_rest + pl, x, y, a.nx, a.ny, a.walls);
+  source_offsets(vy, r.bot, r.top, e);
+  const R psi = restream(q, e, vy.c);
   R *out = reinterpret_cast<R *>(a.scratch + 5 * pl);
-  const R phi = sum9(f), psi = sum9(g);
   out[k] = phi;
   out[pl + k] = psi;
   out[2 * pl + k] = sigma_of(p, psi);
@@ -396,34 +543,33 @@ lbm_macro_scalars_kernel(const SiteArgs a, const Phys<R> p) {
 
 // Read-back, pass 2: u and P by the same closures as the step, float64
 // phi, psi, ux, uy, P into scratch planes 0-4.
-template <class S, class R, bool HAS_S>
+template <class P, bool HAS_S>
 __global__ void __launch_bounds__(256)
-lbm_macro_fields_kernel(const SiteArgs a, const Phys<R> p) {
+lbm_macro_fields_kernel(const SiteArgs<P> a, const Phys<typename P::R> p) {
+  using R = typename P::R;
   const long long n = (long long)a.nx * a.ny;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int x = int(k % a.nx), y = int(k / a.nx);
   const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
-  const S *src = static_cast<const S *>(a.src);
-  const S *aux = static_cast<const S *>(a.aux);
   const long long pl = a.plane;
   const R *sc = reinterpret_cast<const R *>(a.scratch + 5 * pl);
-  const Nine<R> vphi = gather9(sc, x, y, a.nx, a.ny, a.walls);
-  const Nine<R> vsig = gather9(sc + 2 * pl, x, y, a.nx, a.ny, a.walls);
+  const Nine<R> vphi = gather9<R, R>(sc, x, y, a.nx, a.ny, a.walls);
+  const Nine<R> vsig = gather9<R, R>(sc + 2 * pl, x, y, a.nx, a.ny, a.walls);
   R gfx, gfy, gsx, gsy;
   grad9(vphi, gfx, gfy);
   grad9(vsig, gsx, gsy);
   const R lphi = lap9(vphi);
-  const R php = R(aux[k]), psp = R(aux[pl + k]);
-  const R uxp = R(aux[2 * pl + k]), uyp = R(aux[3 * pl + k]);
-  const R Sxp = HAS_S ? R(aux[4 * pl + k]) : R(0);
-  const R Syp = HAS_S ? R(aux[5 * pl + k]) : R(0);
+  const R php = R(a.src_rest[k]), psp = R(a.src_rest[pl + k]);
+  const R uxp = R(a.aux[k]), uyp = R(a.aux[pl + k]);
+  const R Sxp = HAS_S ? R(a.aux[2 * pl + k]) : R(0);
+  const R Syp = HAS_S ? R(a.aux[3 * pl + k]) : R(0);
   const RowIdx r = row_index(y, a.nx, a.ny, a.walls);
   R h[8];
-  pull_h(src, pl, r, x, xm, xp, rho_of(p, php), p.uwb, p.uwt, h);
+  pull_h<P>(a.src, pl, r, x, xm, xp, a.sc.hi, rho_of(p, php), p.uwb, p.uwt, h);
   Front<R> s;
-  site_front<R, HAS_S>(p, s, vphi.c, sc[pl + k], vsig.c, gfx, gfy, lphi, gsx,
-                       gsy, h, php, psp, uxp, uyp, Sxp, Syp);
+  site_front<R, HAS_S>(p, s, vphi.c, sc[pl + k], vsig.c, gfx, gfy, lphi, gsx, gsy, h, php,
+                       psp, uxp, uyp, Sxp, Syp);
   a.scratch[k] = double(s.phi);
   a.scratch[pl + k] = double(s.psi);
   a.scratch[2 * pl + k] = double(s.ux);
@@ -444,14 +590,13 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 __global__ void __launch_bounds__(256)
-lbm_reduce_kernel(const SiteArgs a, const Phys<double> p, double *partials) {
-  const long long n = (long long)a.nx * a.ny;
-  const long long pl = a.plane;
+lbm_reduce_kernel(const double *scratch, long long plane, long long n,
+                  const Phys<double> p, double *partials) {
   double acc[kReduceVals] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
        k += (long long)gridDim.x * blockDim.x) {
-    const double phi = a.scratch[k], psi = a.scratch[pl + k];
-    const double ux = a.scratch[2 * pl + k], uy = a.scratch[3 * pl + k];
+    const double phi = scratch[k], psi = scratch[plane + k];
+    const double ux = scratch[2 * plane + k], uy = scratch[3 * plane + k];
     const double rho = rho_of(p, phi);
     const double u2 = ux * ux + uy * uy;
     acc[0] += phi;
@@ -492,33 +637,35 @@ lbm_reduce_final_kernel(const double *partials, int nblocks, double *out) {
 
 // ------------------------------------------------------------------ host
 
-enum Prec { kF64 = LBM_FP64, kF32 = LBM_FP32, kF16 = LBM_FP16DEV };
-
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t storage_size(int prec) {
+  return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2);
+}
+size_t field_size(int prec) { return prec == LBM_FP64 ? 8 : 4; }
 
 struct Layout {
   long long plane;  // elements per plane
-  size_t pop_bytes, aux_bytes, scratch_bytes, partial_bytes, flag_bytes;
-  size_t off_pop[2], off_aux, off_scratch, off_partial, off_flag, total;
+  size_t pop_bytes, rest_bytes, aux_bytes, scratch_bytes, partial_bytes;
+  size_t off_pop[2], off_rest[2], off_aux, off_scratch, off_partial, off_flag, total;
 };
-
-size_t storage_size(int prec) { return prec == kF64 ? 8 : (prec == kF32 ? 4 : 2); }
-size_t aux_size(int prec) { return prec == kF64 ? 8 : 4; }
 
 Layout make_layout(const lbm_params &p) {
   Layout L;
   const long long n = (long long)p.nx * p.ny;
   L.plane = (long long)align_up((size_t)n, 64);
   L.pop_bytes = align_up((size_t)kPlanes * L.plane * storage_size(p.precision), 256);
-  L.aux_bytes = align_up((size_t)kAux * L.plane * aux_size(p.precision), 256);
+  L.rest_bytes = align_up((size_t)kRest * L.plane * field_size(p.precision), 256);
+  L.aux_bytes = align_up((size_t)kAux * L.plane * field_size(p.precision), 256);
   L.scratch_bytes = align_up((size_t)kScratch * L.plane * 8, 256);
   L.partial_bytes = align_up((size_t)(kReduceBlocks + 1) * kReduceVals * 8, 256);
-  L.flag_bytes = 256;
   size_t o = 0;
-  L.off_pop[0] = o;
-  o += L.pop_bytes;
-  L.off_pop[1] = o;
-  o += L.pop_bytes;
+  for (int c = 0; c < 2; ++c) {
+    L.off_pop[c] = o;
+    o += L.pop_bytes;
+    L.off_rest[c] = o;
+    o += L.rest_bytes;
+  }
   L.off_aux = o;
   o += L.aux_bytes;
   L.off_scratch = o;
@@ -526,7 +673,7 @@ Layout make_layout(const lbm_params &p) {
   L.off_partial = o;
   o += L.partial_bytes;
   L.off_flag = o;
-  o += L.flag_bytes;
+  o += 256;
   L.total = o;
   return L;
 }
@@ -539,10 +686,8 @@ const char *validate(const lbm_params *p) {
   if ((long long)p->nx * p->ny > (1LL << 31)) return "grid too large";
   if (p->walls_y != 0 && p->walls_y != 1) return "walls_y must be 0 or 1";
   if (p->eos != LBM_EOS_LINEAR && p->eos != LBM_EOS_LANGMUIR) return "unknown eos";
-  if (p->precision != LBM_FP64 && p->precision != LBM_FP32) {
-    if (p->precision == LBM_FP16DEV) return "FP16-deviation storage is not available";
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32 && p->precision != LBM_FP16DEV)
     return "unknown precision";
-  }
   if (p->reserved != 0) return "reserved must be 0";
   if (!(p->phiA > p->phiB)) return "phiA must exceed phiB";
   if (!(p->W > 0)) return "W must be > 0";
@@ -557,6 +702,13 @@ const char *validate(const lbm_params *p) {
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
       if (!(p->s_free[a][b] > 0 && p->s_free[a][b] < 2)) return "free rates must lie in (0, 2)";
+  for (int a = 0; a < 3; ++a) {
+    const double s = p->fp16_scale[a];
+    if (s == 0) continue;
+    int e;
+    if (!(s > 0) || std::frexp(s, &e) != 0.5 || e < -30 || e > 31)
+      return "fp16_scale entries must be 0 or powers of two in [2^-30, 2^30]";
+  }
   return nullptr;
 }
 
@@ -603,6 +755,29 @@ Phys<R> make_phys(const lbm_params &q) {
   return p;
 }
 
+// Default float16 scales: deviations of f and g are at most a few 1e-2 of
+// their field, h_i are O(w_i (3P + 3 c.rho u)); the scales put the expected
+// magnitudes near 2^4..2^8, well inside float16's normal range.
+void fp16_scales(const lbm_params &q, double out[3]) {
+  const double dflt[3] = {4096.0, 4096.0, 16384.0};
+  for (int a = 0; a < 3; ++a) out[a] = q.fp16_scale[a] > 0 ? q.fp16_scale[a] : dflt[a];
+}
+
+template <class P>
+Scales<P> make_scales(const lbm_params &q) {
+  using R = typename P::R;
+  Scales<P> s;
+  double v[3] = {1.0, 1.0, 1.0};
+  if (P::SCALED) fp16_scales(q, v);
+  s.f = R(v[0]);
+  s.g = R(v[1]);
+  s.h = R(v[2]);
+  s.fi = R(1.0 / v[0]);
+  s.gi = R(1.0 / v[1]);
+  s.hi = R(1.0 / v[2]);
+  return s;
+}
+
 }  // namespace
 
 struct lbm_handle {
@@ -634,16 +809,22 @@ lbm_status hip_check(lbm_handle *h, hipError_t e, const char *what) {
 }
 
 void *pops(lbm_handle *h, int which) { return h->ws + h->L.off_pop[which]; }
+void *rest(lbm_handle *h, int which) { return h->ws + h->L.off_rest[which]; }
 void *auxp(lbm_handle *h) { return h->ws + h->L.off_aux; }
 double *scratch(lbm_handle *h) { return reinterpret_cast<double *>(h->ws + h->L.off_scratch); }
 double *partials(lbm_handle *h) { return reinterpret_cast<double *>(h->ws + h->L.off_partial); }
 int *flagp(lbm_handle *h) { return reinterpret_cast<int *>(h->ws + h->L.off_flag); }
 
-SiteArgs site_args(lbm_handle *h) {
-  SiteArgs a;
-  a.src = pops(h, h->cur);
-  a.aux = auxp(h);
+template <class P>
+SiteArgs<P> site_args(lbm_handle *h) {
+  SiteArgs<P> a;
+  a.src = static_cast<const typename P::S *>(pops(h, h->cur));
+  a.src_rest = static_cast<const typename P::A *>(rest(h, h->cur));
+  a.dst = static_cast<typename P::S *>(pops(h, h->cur));
+  a.dst_rest = static_cast<typename P::A *>(rest(h, h->cur));
+  a.aux = static_cast<typename P::A *>(auxp(h));
   a.scratch = scratch(h);
+  a.sc = make_scales<P>(h->p);
   a.plane = h->L.plane;
   a.nx = h->p.nx;
   a.ny = h->p.ny;
@@ -653,21 +834,24 @@ SiteArgs site_args(lbm_handle *h) {
 
 int default_rows(const lbm_params &p) {
   const long long strips = (p.nx + kStrip - 1) / kStrip;
-  // aim for at least ~8192 wavefronts in flight on large grids, but keep
-  // tiles tall enough that the two extra halo rows stay a small overhead
+  // aim for at least ~8192 wavefronts on large grids, but keep tiles tall
+  // enough that the two extra halo rows stay a small overhead
   long long rows = strips * p.ny / 8192;
   if (rows < 8) rows = 8;
   if (rows > 64) rows = 64;
   return int(rows);
 }
 
-template <class S, class R, bool GENR, bool HAS_S>
+template <class P, bool GENR, bool HAS_S>
 hipError_t launch_step(lbm_handle *h) {
-  StepArgs<R> a;
-  a.p = make_phys<R>(h->p);
-  a.src = pops(h, h->cur);
-  a.dst = pops(h, h->cur ^ 1);
-  a.aux = auxp(h);
+  StepArgs<P> a;
+  a.p = make_phys<typename P::R>(h->p);
+  a.sc = make_scales<P>(h->p);
+  a.src = static_cast<const typename P::S *>(pops(h, h->cur));
+  a.src_rest = static_cast<const typename P::A *>(rest(h, h->cur));
+  a.dst = static_cast<typename P::S *>(pops(h, h->cur ^ 1));
+  a.dst_rest = static_cast<typename P::A *>(rest(h, h->cur ^ 1));
+  a.aux = static_cast<typename P::A *>(auxp(h));
   a.flag = flagp(h);
   a.plane = h->L.plane;
   a.nx = h->p.nx;
@@ -677,38 +861,67 @@ hipError_t launch_step(lbm_handle *h) {
   a.rows = h->rows;
   a.ntiles = a.nstrips * ((h->p.ny + a.rows - 1) / a.rows);
   const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((lbm_step_kernel<S, R, GENR, HAS_S>), dim3(blocks),
+  hipLaunchKernelGGL((lbm_step_kernel<P, GENR, HAS_S>), dim3(blocks),
                      dim3(kWave * kWavesPerBlock), 0, h->stream, a);
   return hipGetLastError();
 }
 
-template <class S, class R>
+template <class P>
 hipError_t launch_step_prec(lbm_handle *h) {
   if (h->genr)
-    return h->has_s ? launch_step<S, R, true, true>(h) : launch_step<S, R, true, false>(h);
-  return h->has_s ? launch_step<S, R, false, true>(h) : launch_step<S, R, false, false>(h);
+    return h->has_s ? launch_step<P, true, true>(h) : launch_step<P, true, false>(h);
+  return h->has_s ? launch_step<P, false, true>(h) : launch_step<P, false, false>(h);
 }
 
-template <class S, class R>
+hipError_t run_step(lbm_handle *h) {
+  switch (h->p.precision) {
+    case LBM_FP64: return launch_step_prec<F64>(h);
+    case LBM_FP32: return launch_step_prec<F32>(h);
+    default: return launch_step_prec<F16>(h);
+  }
+}
+
+template <class P>
 hipError_t launch_macros(lbm_handle *h) {
-  SiteArgs a = site_args(h);
+  SiteArgs<P> a = site_args<P>(h);
   const long long n = (long long)h->p.nx * h->p.ny;
   const int blocks = int((n + 255) / 256);
-  const Phys<R> p = make_phys<R>(h->p);
-  hipLaunchKernelGGL((lbm_macro_scalars_kernel<S, R>), dim3(blocks), dim3(256), 0,
-                     h->stream, a, p);
+  const Phys<typename P::R> p = make_phys<typename P::R>(h->p);
+  hipLaunchKernelGGL((lbm_macro_scalars_kernel<P>), dim3(blocks), dim3(256), 0, h->stream,
+                     a, p);
   if (h->has_s)
-    hipLaunchKernelGGL((lbm_macro_fields_kernel<S, R, true>), dim3(blocks), dim3(256),
-                       0, h->stream, a, p);
+    hipLaunchKernelGGL((lbm_macro_fields_kernel<P, true>), dim3(blocks), dim3(256), 0,
+                       h->stream, a, p);
   else
-    hipLaunchKernelGGL((lbm_macro_fields_kernel<S, R, false>), dim3(blocks), dim3(256),
-                       0, h->stream, a, p);
+    hipLaunchKernelGGL((lbm_macro_fields_kernel<P, false>), dim3(blocks), dim3(256), 0,
+                       h->stream, a, p);
   return hipGetLastError();
 }
 
 hipError_t run_macros(lbm_handle *h) {
-  return h->p.precision == kF64 ? launch_macros<double, double>(h)
-                                : launch_macros<float, float>(h);
+  switch (h->p.precision) {
+    case LBM_FP64: return launch_macros<F64>(h);
+    case LBM_FP32: return launch_macros<F32>(h);
+    default: return launch_macros<F16>(h);
+  }
+}
+
+template <class P>
+hipError_t launch_init(lbm_handle *h) {
+  SiteArgs<P> a = site_args<P>(h);
+  const long long n = (long long)h->p.nx * h->p.ny;
+  const Phys<double> p = make_phys<double>(h->p);
+  hipLaunchKernelGGL((lbm_init_kernel<P>), dim3(int((n + 255) / 256)), dim3(256), 0,
+                     h->stream, a, p);
+  return hipGetLastError();
+}
+
+hipError_t run_init(lbm_handle *h) {
+  switch (h->p.precision) {
+    case LBM_FP64: return launch_init<F64>(h);
+    case LBM_FP32: return launch_init<F32>(h);
+    default: return launch_init<F16>(h);
+  }
 }
 
 // Reads the sticky device flag (synchronising); marks the state invalid.
@@ -780,17 +993,8 @@ lbm_status lbm_init_fields(lbm_handle *h, const double *phi, const double *psi,
                                   hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) return hip_check(h, e, "copying initial fields");
   }
-  SiteArgs a = site_args(h);
-  const Phys<double> p = make_phys<double>(h->p);
-  const int blocks = int((n + 255) / 256);
   h->cur = 0;
-  if (h->p.precision == kF64)
-    hipLaunchKernelGGL((lbm_init_kernel<double>), dim3(blocks), dim3(256), 0,
-                       h->stream, a, p, static_cast<double *>(pops(h, 0)));
-  else
-    hipLaunchKernelGGL((lbm_init_kernel<float>), dim3(blocks), dim3(256), 0,
-                       h->stream, a, p, static_cast<float *>(pops(h, 0)));
-  hipError_t e = hipGetLastError();
+  hipError_t e = run_init(h);
   if (e == hipSuccess) e = hipMemsetAsync(flagp(h), 0, sizeof(int), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_check(h, e, "initialising");
@@ -804,8 +1008,7 @@ lbm_status lbm_step(lbm_handle *h, int64_t nsteps) {
   if (nsteps < 0) return fail(h, LBM_EINVAL, "nsteps < 0");
   if (!h->valid) return fail(h, LBM_ESTATE, "no valid state");
   for (int64_t t = 0; t < nsteps; ++t) {
-    hipError_t e = h->p.precision == kF64 ? launch_step_prec<double, double>(h)
-                                          : launch_step_prec<float, float>(h);
+    hipError_t e = run_step(h);
     if (e != hipSuccess) return hip_check(h, e, "launching the step kernel");
     h->cur ^= 1;
     h->step += 1;
@@ -841,11 +1044,11 @@ lbm_status lbm_moments(lbm_handle *h, lbm_moments_t *out) {
   if (st != LBM_OK) return st;
   hipError_t e = run_macros(h);
   if (e != hipSuccess) return hip_check(h, e, "launching read-back kernels");
-  SiteArgs a = site_args(h);
   const Phys<double> p = make_phys<double>(h->p);
   double *part = partials(h);
+  const long long n = (long long)h->p.nx * h->p.ny;
   hipLaunchKernelGGL(lbm_reduce_kernel, dim3(kReduceBlocks), dim3(256), 0, h->stream,
-                     a, p, part);
+                     (const double *)scratch(h), h->L.plane, n, p, part);
   hipLaunchKernelGGL(lbm_reduce_final_kernel, dim3(1), dim3(64), 0, h->stream,
                      (const double *)part, kReduceBlocks, part + kReduceBlocks * kReduceVals);
   e = hipGetLastError();
@@ -873,7 +1076,7 @@ lbm_status lbm_moments(lbm_handle *h, lbm_moments_t *out) {
 
 size_t lbm_state_bytes(const lbm_handle *h) {
   if (!h) return 0;
-  return sizeof(int64_t) + h->L.pop_bytes + h->L.aux_bytes;
+  return sizeof(int64_t) + h->L.pop_bytes + h->L.rest_bytes + h->L.aux_bytes;
 }
 
 lbm_status lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
@@ -884,11 +1087,14 @@ lbm_status lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
   if (st != LBM_OK) return st;
   char *b = static_cast<char *>(host_buf);
   std::memcpy(b, &h->step, sizeof(int64_t));
-  hipError_t e = hipMemcpyAsync(b + sizeof(int64_t), pops(h, h->cur), h->L.pop_bytes,
-                                hipMemcpyDeviceToHost, h->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(b + sizeof(int64_t) + h->L.pop_bytes, auxp(h), h->L.aux_bytes,
-                       hipMemcpyDeviceToHost, h->stream);
+  b += sizeof(int64_t);
+  const void *parts[3] = {pops(h, h->cur), rest(h, h->cur), auxp(h)};
+  const size_t sizes[3] = {h->L.pop_bytes, h->L.rest_bytes, h->L.aux_bytes};
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < 3 && e == hipSuccess; ++j) {
+    e = hipMemcpyAsync(b, parts[j], sizes[j], hipMemcpyDeviceToHost, h->stream);
+    b += sizes[j];
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   return hip_check(h, e, "saving state");
 }
@@ -899,12 +1105,15 @@ lbm_status lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
   const char *b = static_cast<const char *>(host_buf);
   int64_t step;
   std::memcpy(&step, b, sizeof(int64_t));
+  b += sizeof(int64_t);
   h->cur = 0;
-  hipError_t e = hipMemcpyAsync(pops(h, 0), b + sizeof(int64_t), h->L.pop_bytes,
-                                hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(auxp(h), b + sizeof(int64_t) + h->L.pop_bytes, h->L.aux_bytes,
-                       hipMemcpyHostToDevice, h->stream);
+  void *parts[3] = {pops(h, 0), rest(h, 0), auxp(h)};
+  const size_t sizes[3] = {h->L.pop_bytes, h->L.rest_bytes, h->L.aux_bytes};
+  hipError_t e = hipSuccess;
+  for (int j = 0; j < 3 && e == hipSuccess; ++j) {
+    e = hipMemcpyAsync(parts[j], b, sizes[j], hipMemcpyHostToDevice, h->stream);
+    b += sizes[j];
+  }
   if (e == hipSuccess) e = hipMemsetAsync(flagp(h), 0, sizeof(int), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_check(h, e, "restoring state");

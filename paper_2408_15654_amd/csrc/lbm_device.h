@@ -69,12 +69,14 @@ __device__ __forceinline__ void grad9(const Nine<R>& v, R& gx, R& gy) {
   gy = third * (v.n - v.m) + twelfth * ((v.nR + v.nL) - (v.mR + v.mL));
 }
 
-// lap X = sum_i 2 w_i (X(x + c_i) - X(x)) / c_s^2.
+// lap X = sum_i 2 w_i (X(x + c_i) - X(x)) / c_s^2, summed as differences
+// from the centre value (exact for close values) to limit cancellation.
 template <class R>
 __device__ __forceinline__ R lap9(const Nine<R>& v) {
-  const R a = R(2) / R(3), b = R(1) / R(6), c = R(10) / R(3);
-  return a * ((v.cR + v.cL) + (v.n + v.m)) + b * ((v.nR + v.nL) + (v.mR + v.mL)) -
-         c * v.c;
+  const R a = R(2) / R(3), b = R(1) / R(6);
+  const R c = v.c;
+  return a * (((v.cR - c) + (v.cL - c)) + ((v.n - c) + (v.m - c))) +
+         b * (((v.nR - c) + (v.nL - c)) + ((v.mR - c) + (v.mL - c)));
 }
 
 // Everything the closures and the sources need at one site.
@@ -170,42 +172,69 @@ __device__ __forceinline__ void site_front(const Phys<R>& p, Front<R>& s, R phi,
 }
 
 // MRT collision of a convection-diffusion LB (Eqs. (21), (25)) in raw-moment
-// space.  Equilibrium w_i X (1 + 3 c_i.u); source w_i c_i.V with
-// V = 3 d_t(X u) + (flux term); rates s1 (first moments), s2 (second), s3
-// (third), s4 (fourth).  In place on f[0..8].
+// space, on DEVIATIONS d_i = f_i - w_i X from the rest equilibrium of the
+// site's own value X = sum f_i.  The rest part w_i X has moments
+// (X, 0, 0, X/3, X/3, 0, 0, 0, X/9), all of which the collision keeps, so
+// only the deviations are relaxed:
+//   m_eq - m_rest = (0, X ux, X uy, 0, 0, 0, X ux/3, X uy/3, 0),
+//   m_F           = (0, Vx/3, Vy/3, 0, 0, 0, Vx/9, Vy/9, 0),
+// with the source w_i c_i.V, V = 3 d_t(X u) + (flux term).  Rates s1 (first
+// moments), s2 (second), s3 (third), s4 (fourth).  The post-collision
+// zeroth deviation moment is 0 (m0 = X is conserved).  In place on d[0..8].
+// Working on deviations keeps every intermediate small, so low-precision
+// arithmetic and storage lose little absolute accuracy.
 template <class R>
-__device__ __forceinline__ void collide_cde(R* f, R X, R ux, R uy, R Vx, R Vy,
+__device__ __forceinline__ void collide_cde(R* d, R X, R ux, R uy, R Vx, R Vy,
                                             R s1, R s2, R s3, R s4) {
-  const R a57 = f[5] + f[7], a68 = f[6] + f[8];
-  const R d57 = f[5] - f[7], d68 = f[6] - f[8];
+  const R a57 = d[5] + d[7], a68 = d[6] + d[8];
+  const R d57 = d[5] - d[7], d68 = d[6] - d[8];
   R m5 = a57 - a68, m8 = a57 + a68;
   R m6 = d57 - d68, m7 = d57 + d68;
-  R m1 = (f[1] - f[3]) + m6, m2 = (f[2] - f[4]) + m7;
-  R m3 = (f[1] + f[3]) + m8, m4 = (f[2] + f[4]) + m8;
+  R m1 = (d[1] - d[3]) + m6, m2 = (d[2] - d[4]) + m7;
+  R m3 = (d[1] + d[3]) + m8, m4 = (d[2] + d[4]) + m8;
   const R third = R(1) / R(3), ninth = R(1) / R(9);
-  const R Xux = X * ux, Xuy = X * uy, X3 = X * third;
-  // m* = m - S (m - m_eq) + (I - S/2) m_F, with
-  // m_eq = (X, X ux, X uy, X/3, X/3, 0, X ux/3, X uy/3, X/9),
-  // m_F  = (0, Vx/3, Vy/3, 0, 0, 0, Vx/9, Vy/9, 0).
+  const R Xux = X * ux, Xuy = X * uy;
   const R h1 = R(1) - R(0.5) * s1, h3 = R(1) - R(0.5) * s3;
   m1 = m1 - s1 * (m1 - Xux) + h1 * (Vx * third);
   m2 = m2 - s1 * (m2 - Xuy) + h1 * (Vy * third);
-  m3 = m3 - s2 * (m3 - X3);
-  m4 = m4 - s2 * (m4 - X3);
+  m3 = m3 - s2 * m3;
+  m4 = m4 - s2 * m4;
   m5 = m5 - s2 * m5;
   m6 = m6 - s3 * (m6 - Xux * third) + h3 * (Vx * ninth);
   m7 = m7 - s3 * (m7 - Xuy * third) + h3 * (Vy * ninth);
-  m8 = m8 - s4 * (m8 - X * ninth);
-  // f = M^-1 m (m0 = X is conserved)
-  f[0] = X - m3 - m4 + m8;
-  f[1] = R(0.5) * (m1 + m3 - m6 - m8);
-  f[2] = R(0.5) * (m2 + m4 - m7 - m8);
-  f[3] = R(0.5) * (-m1 + m3 + m6 - m8);
-  f[4] = R(0.5) * (-m2 + m4 + m7 - m8);
-  f[5] = R(0.25) * (m5 + m6 + m7 + m8);
-  f[6] = R(0.25) * (-m5 - m6 + m7 + m8);
-  f[7] = R(0.25) * (m5 - m6 - m7 + m8);
-  f[8] = R(0.25) * (-m5 + m6 - m7 + m8);
+  m8 = m8 - s4 * m8;
+  // d = M^-1 m with m0 = 0
+  d[0] = -m3 - m4 + m8;
+  d[1] = R(0.5) * (m1 + m3 - m6 - m8);
+  d[2] = R(0.5) * (m2 + m4 - m7 - m8);
+  d[3] = R(0.5) * (-m1 + m3 + m6 - m8);
+  d[4] = R(0.5) * (-m2 + m4 + m7 - m8);
+  d[5] = R(0.25) * (m5 + m6 + m7 + m8);
+  d[6] = R(0.25) * (-m5 - m6 + m7 + m8);
+  d[7] = R(0.25) * (m5 - m6 - m7 + m8);
+  d[8] = R(0.25) * (-m5 + m6 - m7 + m8);
+}
+
+// Streaming in deviation form.  Population i arriving at a site comes from
+// source site s_i with stored deviation dsrc_i (relative to w_i X(s_i)); e_i
+// = X(s_i) - Xc is the source's rest value relative to the site's own old
+// value Xc.  The new zeroth moment is
+//   X' = sum_i (w_i X(s_i) + dsrc_i) = Xc + sum_i w_i e_i + sum_i dsrc_i
+// and the deviations relative to w_i X' are dsrc_i + w_i (e_i - (X' - Xc)).
+// Everything except the final X' is formed from small differences.
+template <class R>
+__device__ __forceinline__ R restream(R* d, const R* e, R Xc) {
+  const R w0 = R(4) / R(9), w1 = R(1) / R(9), w5 = R(1) / R(36);
+  const R se = w0 * e[0] + w1 * ((e[1] + e[2]) + (e[3] + e[4])) +
+               w5 * ((e[5] + e[6]) + (e[7] + e[8]));
+  const R sd = ((d[0] + (d[1] + d[2])) + (d[3] + d[4])) + ((d[5] + d[6]) + (d[7] + d[8]));
+  const R dX = se + sd;
+  d[0] += w0 * (e[0] - dX);
+#pragma unroll
+  for (int i = 1; i < 5; ++i) d[i] += w1 * (e[i] - dX);
+#pragma unroll
+  for (int i = 5; i < 9; ++i) d[i] += w5 * (e[i] - dX);
+  return Xc + dX;
 }
 
 // MRT collision of the flow LB (Eq. (29)) on h_1..h_8 (h[k] = h_{k+1}),

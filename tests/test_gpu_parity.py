@@ -1,8 +1,12 @@
 """Parity of the HIP library (through the C ABI) with the FP64 CPU oracle.
 
-Relative L-infinity error e(X) = max|X_gpu - X_oracle| / max|X_oracle| per
-field.  Bars: 1e-12 for float64 storage, 1e-5 for float32 storage on phi,
-psi and u.  Inputs are the seeded synthetic problems of workloads.py.
+Relative L-infinity error per field: e(X) = max|X_gpu - X_oracle| /
+max|X_oracle| for phi, psi and P; for the velocity the vector form
+e(u) = max|u_gpu - u_oracle| / max|u_oracle| (|.| the Euclidean norm), so a
+small cross-flow component is measured against the flow speed.  Bars: 1e-12
+for float64 storage, 1e-5 for float32 storage on phi, psi and u, 1e-3 for
+float16-deviation storage.  Inputs are the seeded synthetic problems of
+workloads.py.
 """
 import numpy as np
 import pytest
@@ -12,13 +16,25 @@ from paper_2408_15654_amd import lbm, workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-5}
-FIELDS = ("phi", "psi", "ux", "uy")
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp16dev": 1e-3}
+FIELDS = ("phi", "psi", "u")
 
 
 def rel_linf(a, b):
     s = np.abs(b).max()
     return float(np.abs(a - b).max() / (s if s > 0 else 1.0))
+
+
+def errors(got, want, fields):
+    out = {}
+    for k in fields:
+        if k == "u":
+            d = np.hypot(got["ux"] - want["ux"], got["uy"] - want["uy"])
+            s = np.hypot(want["ux"], want["uy"]).max()
+            out[k] = float(d.max() / (s if s > 0 else 1.0))
+        else:
+            out[k] = rel_linf(got[k], want[k])
+    return out
 
 
 def run_gpu(pr, precision, steps, rows=None):
@@ -38,13 +54,13 @@ def run_oracle(pr, steps):
 
 
 def check(got, want, tol, label, fields=FIELDS):
-    errs = {k: rel_linf(got[k], want[k]) for k in fields}
+    errs = errors(got, want, fields)
     print(label, " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
     for k, e in errs.items():
         assert e <= tol, (label, k, e)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
 def test_initial_level_matches_oracle(precision):
     pr = W.c1_stationary_drop()
     _, got = run_gpu(pr, precision, 0)
@@ -52,7 +68,7 @@ def test_initial_level_matches_oracle(precision):
     check(got, want, TOL[precision], f"init {precision}", FIELDS + ("P",))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
 def test_drop64_full_run(precision):
     """64x64 drop, 2000 steps (the full run of the small configuration)."""
     pr = W.c1_stationary_drop()
@@ -98,7 +114,8 @@ def test_ragged_and_tiny_grids(nx, ny):
     check(got, want, 1e-12, f"grid {nx}x{ny}")
 
 
-@pytest.mark.parametrize("precision,beta", [("fp64", 0.5), ("fp32", 0.5), ("fp64", 0.0)])
+@pytest.mark.parametrize("precision,beta", [("fp64", 0.5), ("fp32", 0.5), ("fp16dev", 0.5),
+                                            ("fp64", 0.0)])
 def test_shear_drop(precision, beta):
     """256x128 channel between moving walls, drop R=32 (300 steps)."""
     pr = W.c2_shear_drop(beta=beta)
@@ -107,7 +124,7 @@ def test_shear_drop(precision, beta):
     check(got, want, TOL[precision], f"shear {precision} beta={beta}")
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
 def test_many_drops_full_size(precision):
     """2048x2048, 400 drops, density ratio 10, in the launch configuration
     the benchmark times: every site compared after 2 steps."""
@@ -125,7 +142,7 @@ def test_tile_height_does_not_change_results():
         _, got = run_gpu(pr, "fp64", pr.steps, rows=rows)
         outs.append(got)
     for o in outs[1:]:
-        for k in FIELDS + ("P",):
+        for k in ("phi", "psi", "ux", "uy", "P"):
             assert np.array_equal(o[k], outs[0][k]), k
 
 
@@ -142,7 +159,7 @@ def test_checkpoint_restore_is_bitwise():
     assert sim.moments()["step"] == 10
     sim.step(20)
     b = sim.read_fields()
-    for k in FIELDS + ("P",):
+    for k in ("phi", "psi", "ux", "uy", "P"):
         assert np.array_equal(a[k], b[k]), k
 
 
