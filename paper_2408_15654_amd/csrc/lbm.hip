@@ -1,8 +1,11 @@
 // HIP kernels and C ABI of the coupled three-field lattice Boltzmann library
 // (phase field f, surfactant g, flow h; arXiv:2408.15654), for gfx950.
 //
-// State on the device (structure of arrays, x fastest, one plane per
-// quantity, planes padded to 64 elements), two copies (ping-pong):
+// State on the device, row-interleaved structure of arrays: for each row y
+// the rows of all planes of a group follow each other (element (plane q,
+// row y, column x) of a group of NP planes is at (y*NP + q)*nx + x), so one
+// lattice row of every population lies in one contiguous block.  Two
+// copies (ping-pong) of:
 //   populations  planes 0-8: deviations d_i = f_i - w_i phi of the
 //                post-collision phase-field populations from the rest
 //                equilibrium of their own site; 9-17: the same for g with
@@ -13,13 +16,14 @@
 //   aux          planes ux, uy, Sx, Sy of the previous time level (the
 //                first-order time differences need them; phi, psi come from
 //                the rest planes);
-//   scratch      float64 planes for host transfers and read-back.
+//   scratch      float64 planes (plane-major) for host transfers and
+//                read-back.
 // Storage type: float64, float32, or float16 with per-field power-of-two
 // scales (deviations and h are small numbers; phi, psi stay float32).
 //
 // One time step is ONE launch of lbm_step_kernel.  Each wavefront owns a
-// strip of 62 columns (plus one halo column on each side, lanes 0 and
-// w+1) and walks down a tile of rows.  For each row it pulls the f and g
+// strip of 60 columns (plus two halo columns on each side) and walks down a
+// tile of rows.  For each row it pulls the f and g
 // deviations of the NEXT row, rebuilds that row's phi, psi (and sigma(psi))
 // from them and the rest values of their source sites, keeps a three-row
 // window of phi, psi, sigma in registers and takes x-neighbours from
@@ -43,7 +47,6 @@ using namespace lbm;
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kStrip = kWave - 2;  // interior columns per wavefront
 constexpr int kWavesPerBlock = 4;
 constexpr int kPlanes = 26;
 constexpr int kRest = 2;
@@ -79,6 +82,105 @@ struct Scales {
   typename P::R fi, gi, hi;  // multiply after loading
 };
 
+// Element at a 32-bit byte offset from a (wave-uniform) base pointer: the
+// address is then an SGPR base plus one VGPR offset.
+template <class T>
+__device__ __forceinline__ const T &at(const T *base, unsigned byte_off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ T &at(T *base, unsigned byte_off) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+}
+
+template <class P>
+__device__ __forceinline__ typename P::R ldb(const typename P::S *p, unsigned byte_off,
+                                             typename P::R inv) {
+  using R = typename P::R;
+  if constexpr (P::SCALED)
+    return R(at(p, byte_off)) * inv;
+  else
+    return R(at(p, byte_off));
+}
+template <class P>
+__device__ __forceinline__ void stb(typename P::S *p, unsigned byte_off, typename P::R v,
+                                    typename P::R scale) {
+  using S = typename P::S;
+  if constexpr (P::SCALED)
+    at(p, byte_off) = S(v * scale);
+  else
+    at(p, byte_off) = S(v);
+}
+
+// Buffer-resource memory access for the step kernel: the address is a
+// wave-uniform resource (SGPRs) plus a uniform byte offset (SGPR) plus one
+// per-lane 32-bit byte offset (VGPR), so no per-lane 64-bit address math.
+// The third dword 0x00020000 is the raw 32-bit-element format of gfx9-family
+// buffer descriptors.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes),
+                                           0x00020000);
+}
+
+template <class T>
+struct BufIO;
+template <>
+struct BufIO<float> {
+  static __device__ __forceinline__ float load(rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void store(float x, rsrc_t r, unsigned v, unsigned s) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+  }
+};
+template <>
+struct BufIO<double> {
+  static __device__ __forceinline__ double load(rsrc_t r, unsigned v, unsigned s) {
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0);
+    const unsigned w0 = w[0], w1 = w[1];
+    return __hiloint2double(int(w1), int(w0));
+  }
+  static __device__ __forceinline__ void store(double x, rsrc_t r, unsigned v, unsigned s) {
+    u32x2 w;
+    w[0] = unsigned(__double2loint(x));
+    w[1] = unsigned(__double2hiint(x));
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, v, s, 0);
+  }
+};
+template <>
+struct BufIO<_Float16> {
+  static __device__ __forceinline__ _Float16 load(rsrc_t r, unsigned v, unsigned s) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void store(_Float16 x, rsrc_t r, unsigned v, unsigned s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, 0);
+  }
+};
+
+// Population load / store through a buffer resource, with the float16
+// scale where the storage is scaled.
+template <class P>
+__device__ __forceinline__ typename P::R bld(rsrc_t r, unsigned v, unsigned s,
+                                             typename P::R inv) {
+  using R = typename P::R;
+  if constexpr (P::SCALED)
+    return R(BufIO<typename P::S>::load(r, v, s)) * inv;
+  else
+    return R(BufIO<typename P::S>::load(r, v, s));
+}
+template <class P>
+__device__ __forceinline__ void bst(typename P::R x, rsrc_t r, unsigned v, unsigned s,
+                                    typename P::R scale) {
+  using S = typename P::S;
+  if constexpr (P::SCALED)
+    BufIO<S>::store(S(x * scale), r, v, s);
+  else
+    BufIO<S>::store(S(x), r, v, s);
+}
+
 template <class P>
 __device__ __forceinline__ typename P::R ld(const typename P::S *p, long long i,
                                             typename P::R inv) {
@@ -108,7 +210,6 @@ struct StepArgs {
   typename P::A *dst_rest;
   typename P::A *aux;
   int *flag;
-  long long plane;
   int nx, ny, walls;
   int nstrips, ntiles, rows;
 };
@@ -140,44 +241,103 @@ __device__ __forceinline__ int wrap_row(int y, int ny, int walls) {
   return y < 0 ? y + ny : (y >= ny ? y - ny : y);
 }
 
-// Pull streaming of one 9-population field to site (x, row): population i
-// comes from x - c_i; across a wall it is the opposite population of the
-// site itself (half-way bounce-back, no flux).
-template <class P>
-__device__ __forceinline__ void pull9(const typename P::S *__restrict__ s, long long pl,
-                                      const RowIdx &r, int x, int xm, int xp,
-                                      typename P::R inv, typename P::R *f) {
-  f[0] = ld<P>(s, r.rc + x, inv);
-  f[1] = ld<P>(s, pl + r.rc + xm, inv);
-  f[2] = r.bot ? ld<P>(s, 4 * pl + r.rc + x, inv) : ld<P>(s, 2 * pl + r.rm + x, inv);
-  f[3] = ld<P>(s, 3 * pl + r.rc + xp, inv);
-  f[4] = r.top ? ld<P>(s, 2 * pl + r.rc + x, inv) : ld<P>(s, 4 * pl + r.rp + x, inv);
-  f[5] = r.bot ? ld<P>(s, 7 * pl + r.rc + x, inv) : ld<P>(s, 5 * pl + r.rm + xm, inv);
-  f[6] = r.bot ? ld<P>(s, 8 * pl + r.rc + x, inv) : ld<P>(s, 6 * pl + r.rm + xp, inv);
-  f[7] = r.top ? ld<P>(s, 5 * pl + r.rc + x, inv) : ld<P>(s, 7 * pl + r.rp + xp, inv);
-  f[8] = r.top ? ld<P>(s, 6 * pl + r.rc + x, inv) : ld<P>(s, 8 * pl + r.rp + xm, inv);
+// ------------------------------------------------------------------
+// Memory layout (row-interleaved; x fastest inside each block).  Row y of
+// the population group holds, in units of the storage type S:
+//   block FG: for i = 0..8, nx pairs (f_i, g_i)      -> 18 nx values
+//   block H:  for i = 1..8, nx values h_i             ->  8 nx values
+// so f_i and g_i, which stream from the same source site, arrive in one
+// load.  The rest group holds (phi, psi) pairs and the aux group
+// (ux, uy, Sx, Sy) quadruples, one per site.
+__device__ __forceinline__ long long fg_idx(int i, int c, int y, int x, int nx) {
+  return (long long)y * (kPlanes * nx) + (long long)(i * nx + x) * 2 + c;
+}
+__device__ __forceinline__ long long h_idx(int i, int y, int x, int nx) {
+  return (long long)y * (kPlanes * nx) + 18LL * nx + (long long)(i - 1) * nx + x;
+}
+__device__ __forceinline__ long long rest_idx(int c, int y, int x, int nx) {
+  return ((long long)y * nx + x) * kRest + c;
+}
+__device__ __forceinline__ long long aux_idx(int c, int y, int x, int nx) {
+  return ((long long)y * nx + x) * kAux + c;
 }
 
-// Pull of h_1..h_8 (planes 18-25); across a wall, bounce-back with Ladd's
+// Rows y-1, y, y+1 to pull from (valid even at walls) and the wall flags of
+// row y.
+struct RowN {
+  int m, c, p;
+  bool bot, top;
+};
+
+__device__ __forceinline__ RowN row_numbers(int y, int ny, int walls) {
+  const RowIdx r = row_index(y, 1, ny, walls);
+  RowN n;
+  n.m = int(r.rm);
+  n.c = int(r.rc);
+  n.p = int(r.rp);
+  n.bot = r.bot;
+  n.top = r.top;
+  return n;
+}
+
+// Source (row, column, direction) of population i pulled to site (x, row
+// r.c): x - c_i, or across a wall the opposite population of the site
+// itself (half-way bounce-back).
+struct Src {
+  int y, x, dir;
+};
+__device__ __forceinline__ Src pull_source(int i, const RowN &r, int x, int xm, int xp) {
+  switch (i) {
+    case 0: return {r.c, x, 0};
+    case 1: return {r.c, xm, 1};
+    case 3: return {r.c, xp, 3};
+    case 2: return r.bot ? Src{r.c, x, 4} : Src{r.m, x, 2};
+    case 5: return r.bot ? Src{r.c, x, 7} : Src{r.m, xm, 5};
+    case 6: return r.bot ? Src{r.c, x, 8} : Src{r.m, xp, 6};
+    case 4: return r.top ? Src{r.c, x, 2} : Src{r.p, x, 4};
+    case 7: return r.top ? Src{r.c, x, 5} : Src{r.p, xp, 7};
+    default: return r.top ? Src{r.c, x, 6} : Src{r.p, xm, 8};
+  }
+}
+
+// Pull streaming of f and g to site (x, row) (pointer form, for the
+// per-site kernels).
+template <class P>
+__device__ __forceinline__ void pull_fg(const typename P::S *__restrict__ s, const RowN &r,
+                                        int x, int xm, int xp, int nx, typename P::R fi,
+                                        typename P::R gi, typename P::R *f,
+                                        typename P::R *g) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const Src q = pull_source(i, r, x, xm, xp);
+    f[i] = ld<P>(s, fg_idx(q.dir, 0, q.y, q.x, nx), fi);
+    g[i] = ld<P>(s, fg_idx(q.dir, 1, q.y, q.x, nx), gi);
+  }
+}
+
+// Pull of h_1..h_8 (h[k] = h_{k+1}); across a wall, bounce-back with Ladd's
 // moving-wall term 2 w_i rho_w (c_i.u_w)/c_s^2 = rho_w c_ix u_w / 6 for the
 // diagonal populations (rho_w = rho at the site at collision time).
 template <class P>
-__device__ __forceinline__ void pull_h(const typename P::S *__restrict__ s0, long long pl,
-                                       const RowIdx &r, int x, int xm, int xp,
-                                       typename P::R inv, typename P::R rho_w,
-                                       typename P::R uwb, typename P::R uwt,
-                                       typename P::R *h) {
+__device__ __forceinline__ void pull_h(const typename P::S *__restrict__ s, const RowN &r,
+                                       int x, int xm, int xp, int nx, typename P::R inv,
+                                       typename P::R rho_w, typename P::R uwb,
+                                       typename P::R uwt, typename P::R *h) {
   using R = typename P::R;
-  const typename P::S *s = s0 + 18 * pl;  // s[(i-1) pl] is h_i
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const Src q = pull_source(i, r, x, xm, xp);
+    h[i - 1] = ld<P>(s, h_idx(q.dir, q.y, q.x, nx), inv);
+  }
   const R kb = rho_w * uwb * R(1.0 / 6.0), kt = rho_w * uwt * R(1.0 / 6.0);
-  h[0] = ld<P>(s, r.rc + xm, inv);
-  h[1] = r.bot ? ld<P>(s, 3 * pl + r.rc + x, inv) : ld<P>(s, pl + r.rm + x, inv);
-  h[2] = ld<P>(s, 2 * pl + r.rc + xp, inv);
-  h[3] = r.top ? ld<P>(s, pl + r.rc + x, inv) : ld<P>(s, 3 * pl + r.rp + x, inv);
-  h[4] = r.bot ? ld<P>(s, 6 * pl + r.rc + x, inv) + kb : ld<P>(s, 4 * pl + r.rm + xm, inv);
-  h[5] = r.bot ? ld<P>(s, 7 * pl + r.rc + x, inv) - kb : ld<P>(s, 5 * pl + r.rm + xp, inv);
-  h[6] = r.top ? ld<P>(s, 4 * pl + r.rc + x, inv) - kt : ld<P>(s, 6 * pl + r.rp + xp, inv);
-  h[7] = r.top ? ld<P>(s, 5 * pl + r.rc + x, inv) + kt : ld<P>(s, 7 * pl + r.rp + xm, inv);
+  if (r.bot) {
+    h[4] += kb;
+    h[5] -= kb;
+  }
+  if (r.top) {
+    h[6] -= kt;
+    h[7] += kt;
+  }
 }
 
 // Rest values of the nine source sites of a row r relative to the site's
@@ -198,14 +358,27 @@ __device__ __forceinline__ void source_offsets(const Nine<R> &v, bool bot, bool 
   e[8] = top ? R(0) : v.nL - c;
 }
 
-// Value of lane-1 / lane+1 of the wavefront.
-template <class R>
-__device__ __forceinline__ R from_left(R v) {
-  return __shfl_up(v, 1, kWave);
+// Value of lane-1 / lane+1 of the wavefront: DPP wave shifts (one VALU op
+// per 32 bits; lane 0 / lane 63 receive 0, which is never used).
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
 }
-template <class R>
-__device__ __forceinline__ R from_right(R v) {
-  return __shfl_down(v, 1, kWave);
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x138, 0xf, 0xf, false);
+  return __longlong_as_double((long long)((unsigned long long)(unsigned)lo |
+                                          ((unsigned long long)(unsigned)hi << 32)));
+}
+__device__ __forceinline__ double from_right(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x130, 0xf, 0xf, false);
+  return __longlong_as_double((long long)((unsigned long long)(unsigned)lo |
+                                          ((unsigned long long)(unsigned)hi << 32)));
 }
 
 template <class R>
@@ -223,43 +396,187 @@ __device__ __forceinline__ Nine<R> window(R m, R c, R n) {
   return v;
 }
 
-// One column of an old rest field with its two x-neighbours.  The halo
-// lanes (0 and w+1) have no lane beyond them and read that neighbour.
-template <class R>
-struct Col3 {
-  R L, C, Rt;
+// Pairs through one buffer access.  Vector elements are copied to scalars
+// before any reinterpretation: a bit cast applied directly to an element
+// of an ext_vector reads the vector's first element.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+struct PairIO;
+template <>
+struct PairIO<float> {
+  static __device__ __forceinline__ void load(rsrc_t r, unsigned v, unsigned s, float &a,
+                                              float &b) {
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0);
+    const unsigned w0 = w[0], w1 = w[1];
+    a = __uint_as_float(w0);
+    b = __uint_as_float(w1);
+  }
+  static __device__ __forceinline__ void store(float a, float b, rsrc_t r, unsigned v,
+                                               unsigned s) {
+    u32x2 w;
+    w[0] = __float_as_uint(a);
+    w[1] = __float_as_uint(b);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, v, s, 0);
+  }
+};
+template <>
+struct PairIO<double> {
+  static __device__ __forceinline__ void load(rsrc_t r, unsigned v, unsigned s, double &a,
+                                              double &b) {
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
+    const unsigned w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
+    a = __hiloint2double(int(w1), int(w0));
+    b = __hiloint2double(int(w3), int(w2));
+  }
+  static __device__ __forceinline__ void store(double a, double b, rsrc_t r, unsigned v,
+                                               unsigned s) {
+    u32x4 w;
+    w[0] = unsigned(__double2loint(a));
+    w[1] = unsigned(__double2hiint(a));
+    w[2] = unsigned(__double2loint(b));
+    w[3] = unsigned(__double2hiint(b));
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, v, s, 0);
+  }
+};
+template <>
+struct PairIO<_Float16> {
+  static __device__ __forceinline__ void load(rsrc_t r, unsigned v, unsigned s, _Float16 &a,
+                                              _Float16 &b) {
+    const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+    const unsigned short lo = (unsigned short)(w & 0xffffu), hi = (unsigned short)(w >> 16);
+    a = __builtin_bit_cast(_Float16, lo);
+    b = __builtin_bit_cast(_Float16, hi);
+  }
+  static __device__ __forceinline__ void store(_Float16 a, _Float16 b, rsrc_t r, unsigned v,
+                                               unsigned s) {
+    const unsigned short lo = __builtin_bit_cast(unsigned short, a),
+                         hi = __builtin_bit_cast(unsigned short, b);
+    const unsigned w = unsigned(lo) | (unsigned(hi) << 16);
+    __builtin_amdgcn_raw_buffer_store_b32(w, r, v, s, 0);
+  }
 };
 
-template <class A, class R>
-__device__ __forceinline__ Col3<R> load_col3(const A *__restrict__ a, long long row,
-                                             int x, int xm, int xp, int lane, int w) {
-  Col3<R> c;
-  c.C = R(a[row + x]);
-  c.L = from_left(c.C);
-  c.Rt = from_right(c.C);
-  if (lane == 0) c.L = R(a[row + xm]);
-  if (lane == w + 1) c.Rt = R(a[row + xp]);
-  return c;
+// Byte offsets of one row in the step kernel's three groups.
+struct RowOff {
+  unsigned m, c, p;  // population rows y-1, y, y+1
+  bool bot, top;
+};
+
+__device__ __forceinline__ RowOff row_offsets(int y, int ny, int walls, unsigned row_bytes) {
+  const RowIdx r = row_index(y, 1, ny, walls);
+  RowOff o;
+  o.m = unsigned(r.rm) * row_bytes;
+  o.c = unsigned(r.rc) * row_bytes;
+  o.p = unsigned(r.rp) * row_bytes;
+  o.bot = r.bot;
+  o.top = r.top;
+  return o;
 }
 
+// Per-lane byte offsets of columns x, x-1, x+1 inside a FG block (pairs)
+// and an H block (singles).
+struct ColOff {
+  unsigned p0, pm, pp;  // pairs
+  unsigned h0, hm, hp;  // singles
+};
+
+template <class P>
+struct Pull {
+  using R = typename P::R;
+  using S = typename P::S;
+  // f_i, g_i of the nine populations arriving at row r (one pair load each)
+  static __device__ __forceinline__ void fg(rsrc_t rs, unsigned nxb, const RowOff &r,
+                                            const ColOff &c, const Scales<P> &sc, R *f, R *g) {
+    // nxb: bytes of one pair row (nx pairs)
+    auto pair = [&](int dir, unsigned row, unsigned col, int i) {
+      S a, b;
+      PairIO<S>::load(rs, col, row + unsigned(dir) * nxb, a, b);
+      if constexpr (P::SCALED) {
+        f[i] = R(a) * sc.fi;
+        g[i] = R(b) * sc.gi;
+      } else {
+        f[i] = R(a);
+        g[i] = R(b);
+      }
+    };
+    pair(0, r.c, c.p0, 0);
+    pair(1, r.c, c.pm, 1);
+    pair(3, r.c, c.pp, 3);
+    if (r.bot) {
+      pair(4, r.c, c.p0, 2);
+      pair(7, r.c, c.p0, 5);
+      pair(8, r.c, c.p0, 6);
+    } else {
+      pair(2, r.m, c.p0, 2);
+      pair(5, r.m, c.pm, 5);
+      pair(6, r.m, c.pp, 6);
+    }
+    if (r.top) {
+      pair(2, r.c, c.p0, 4);
+      pair(5, r.c, c.p0, 7);
+      pair(6, r.c, c.p0, 8);
+    } else {
+      pair(4, r.p, c.p0, 4);
+      pair(7, r.p, c.pp, 7);
+      pair(8, r.p, c.pm, 8);
+    }
+  }
+  // h_1..h_8 arriving at row r (h[k] = h_{k+1}); hb: byte offset of the H
+  // block in a row, nxh: bytes of one h row
+  static __device__ __forceinline__ void h(rsrc_t rs, unsigned hb, unsigned nxh,
+                                           const RowOff &r, const ColOff &c, R inv, R *out) {
+    auto one = [&](int dir, unsigned row, unsigned col, int k) {
+      out[k] = bld<P>(rs, col, row + hb + unsigned(dir - 1) * nxh, inv);
+    };
+    one(1, r.c, c.hm, 0);
+    one(3, r.c, c.hp, 2);
+    if (r.bot) {
+      one(4, r.c, c.h0, 1);
+      one(7, r.c, c.h0, 4);
+      one(8, r.c, c.h0, 5);
+    } else {
+      one(2, r.m, c.h0, 1);
+      one(5, r.m, c.hm, 4);
+      one(6, r.m, c.hp, 5);
+    }
+    if (r.top) {
+      one(2, r.c, c.h0, 3);
+      one(5, r.c, c.h0, 6);
+      one(6, r.c, c.h0, 7);
+    } else {
+      one(4, r.p, c.h0, 3);
+      one(7, r.p, c.hp, 6);
+      one(8, r.p, c.hm, 7);
+    }
+  }
+};
+
+// Moving-wall term of the bounced diagonal h populations (see pull_h).
 template <class R>
-__device__ __forceinline__ Nine<R> nine_of(const Col3<R> &m, const Col3<R> &c,
-                                           const Col3<R> &n) {
-  Nine<R> v;
-  v.mL = m.L;
-  v.m = m.C;
-  v.mR = m.Rt;
-  v.cL = c.L;
-  v.c = c.C;
-  v.cR = c.Rt;
-  v.nL = n.L;
-  v.n = n.C;
-  v.nR = n.Rt;
-  return v;
+__device__ __forceinline__ void wall_terms(bool bot, bool top, R rho_w, R uwb, R uwt,
+                                           R *h) {
+  if (bot) {
+    const R kb = rho_w * uwb * R(1.0 / 6.0);
+    h[4] += kb;
+    h[5] -= kb;
+  }
+  if (top) {
+    const R kt = rho_w * uwt * R(1.0 / 6.0);
+    h[6] -= kt;
+    h[7] += kt;
+  }
 }
+
+constexpr int kHalo = 2;                  // halo lanes on each side
+constexpr int kCols = kWave - 2 * kHalo;  // interior columns per wavefront
 
 // The fused step: pull-stream + boundaries, phi/psi/sigma, stencils, forces,
-// closures, three MRT collisions, store.  See the file header.
+// closures, three MRT collisions, store.  Lanes 0-1 and w+2, w+3 are halo
+// columns: they rebuild phi, psi, sigma for the stencils of the interior
+// lanes 2..w+1 but store nothing (lanes 0 and w+3 only serve lanes 1 and
+// w+2, whose rebuild needs the old rest values one column further out).
+// The row loop is software-pipelined: the loads for row y+1 are issued
+// before the arithmetic and stores of row y.
 template <class P, bool GENR, bool HAS_S>
 __global__ void __launch_bounds__(256)
 lbm_step_kernel(const StepArgs<P> a) {
@@ -267,93 +584,154 @@ lbm_step_kernel(const StepArgs<P> a) {
   using S = typename P::S;
   using A = typename P::A;
   const int lane = threadIdx.x & (kWave - 1);
-  const int tile = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  // the wavefront index is the same on every lane: make it a scalar so all
+  // row arithmetic and row offsets stay in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int tile = blockIdx.x * kWavesPerBlock + wave;
   if (tile >= a.ntiles) return;  // whole wavefronts only
   const int nx = a.nx, ny = a.ny, walls = a.walls;
   const int strip = tile % a.nstrips;
   const int chunk = tile / a.nstrips;
-  const int x0 = strip * kStrip;
-  const int w = min(kStrip, nx - x0);
-  const bool interior = lane >= 1 && lane <= w;
-  int xl = x0 - 1 + min(lane, w + 1);
-  const int x = xl < 0 ? xl + nx : (xl >= nx ? xl - nx : xl);
-  const int xm = x == 0 ? nx - 1 : x - 1;
-  const int xp = x == nx - 1 ? 0 : x + 1;
+  const int x0 = strip * kCols;
+  const int w = min(kCols, nx - x0);
+  const bool interior = lane >= kHalo && lane < kHalo + w;
+  int xl = x0 - kHalo + min(lane, w + 2 * kHalo - 1);
+  xl %= nx;
+  if (xl < 0) xl += nx;
+  const unsigned xc = unsigned(xl);
+  const unsigned xcm = xl == 0 ? unsigned(nx - 1) : xc - 1;
+  const unsigned xcp = xl == nx - 1 ? 0u : xc + 1;
+  constexpr unsigned ES = sizeof(S), EA = sizeof(A);
+  ColOff co;
+  co.p0 = xc * 2 * ES;
+  co.pm = xcm * 2 * ES;
+  co.pp = xcp * 2 * ES;
+  co.h0 = xc * ES;
+  co.hm = xcm * ES;
+  co.hp = xcp * ES;
+  const unsigned brest = xc * kRest * EA;  // this site's (phi, psi) pair in a row
+  const unsigned baux = xc * kAux * EA;    // this site's (ux, uy, Sx, Sy)
   const int y0 = chunk * a.rows;
   const int y1 = min(y0 + a.rows, ny);
-  const long long pl = a.plane;
-  const S *__restrict__ src = a.src;
-  const A *__restrict__ rX = a.src_rest;       // old phi
-  const A *__restrict__ rY = a.src_rest + pl;  // old psi
-  S *__restrict__ dst = a.dst;
-  A *__restrict__ aux = a.aux;
+  const unsigned nsites = unsigned(nx) * unsigned(ny);
+  const unsigned nxb = unsigned(nx) * 2 * ES;      // one FG pair row
+  const unsigned nxh = unsigned(nx) * ES;          // one h row
+  const unsigned hb = 9u * nxb;                    // H block offset in a row
+  const unsigned rows_s = unsigned(kPlanes) * nxh; // bytes per population row
+  const unsigned rrow = unsigned(nx) * kRest * EA; // bytes per rest row
+  const unsigned arow = unsigned(nx) * kAux * EA;  // bytes per aux row
+  const rsrc_t rsrc = make_rsrc(a.src, unsigned(kPlanes) * nsites * ES);
+  const rsrc_t rdst = make_rsrc(a.dst, unsigned(kPlanes) * nsites * ES);
+  const rsrc_t rrest = make_rsrc(a.src_rest, unsigned(kRest) * nsites * EA);
+  const rsrc_t rdrest = make_rsrc(a.dst_rest, unsigned(kRest) * nsites * EA);
+  const rsrc_t raux = make_rsrc(a.aux, unsigned(kAux) * nsites * EA);
   const Phys<R> &p = a.p;
   const Scales<P> &sc = a.sc;
 
-  // old rest field at row y (wrapped or clamped) with x-neighbours
-  auto col = [&](const A *f, int y) {
-    return load_col3<A, R>(f, (long long)wrap_row(y, ny, walls) * nx, x, xm, xp, lane, w);
+  // old (phi, psi) of this column at row y, wrapped or clamped
+  auto rest_at = [&](int y, R &X, R &Y) {
+    A u, v;
+    PairIO<A>::load(rrest, brest, unsigned(wrap_row(y, ny, walls)) * rrow, u, v);
+    X = R(u);
+    Y = R(v);
   };
-  // new phi, psi, sigma of row r and its deviations (relative to them),
-  // given the old rest fields at rows r-1, r, r+1
-  auto advance = [&](int r, const Col3<R> &Xm, const Col3<R> &Xc, const Col3<R> &Xn,
-                     const Col3<R> &Ym, const Col3<R> &Yc, const Col3<R> &Yn, R *d,
-                     R *q, R &ph, R &ps, R &sg) {
-    const RowIdx ri = row_index(r, nx, ny, walls);
-    pull9<P>(src, pl, ri, x, xm, xp, sc.fi, d);
-    pull9<P>(src + 9 * pl, pl, ri, x, xm, xp, sc.gi, q);
+  // raw stored deviations of f and g pulled to row r
+  auto load_fg = [&](int r, R *d, R *q) {
+    Pull<P>::fg(rsrc, nxb, row_offsets(r, ny, walls, rows_s), co, sc, d, q);
+  };
+  // loads of row y that the rebuild of row y+1 does not need
+  auto load_row = [&](int y, R *h, R &uxp, R &uyp, R &Sxp, R &Syp) {
+    Pull<P>::h(rsrc, hb, nxh, row_offsets(y, ny, walls, rows_s), co, sc.hi, h);
+    A u, v;
+    PairIO<A>::load(raux, baux, unsigned(y) * arow, u, v);
+    uxp = R(u);
+    uyp = R(v);
+    if (HAS_S) {
+      PairIO<A>::load(raux, baux + 2 * EA, unsigned(y) * arow, u, v);
+      Sxp = R(u);
+      Syp = R(v);
+    } else {
+      Sxp = Syp = R(0);
+    }
+  };
+  // rebuild row r from its raw deviations: new phi, psi, sigma, and the
+  // deviations relative to them (in place), given the old rest fields at
+  // rows r-1, r, r+1 of this column
+  auto rebuild = [&](int r, R Xm, R Xc, R Xn, R Ym, R Yc, R Yn, R *d, R *q, R &ph, R &ps,
+                     R &sg) {
+    const bool bot = walls && r == 0, top = walls && r == ny - 1;
     R e[9];
-    source_offsets(nine_of(Xm, Xc, Xn), ri.bot, ri.top, e);
-    ph = restream(d, e, Xc.C);
-    source_offsets(nine_of(Ym, Yc, Yn), ri.bot, ri.top, e);
-    ps = restream(q, e, Yc.C);
+    source_offsets(window(Xm, Xc, Xn), bot, top, e);
+    ph = restream(d, e, Xc);
+    source_offsets(window(Ym, Yc, Yn), bot, top, e);
+    ps = restream(q, e, Yc);
     sg = sigma_of(p, ps);
   };
+  auto wrap_y = [&](int y) { return y >= ny ? y - ny : y; };
 
-  Col3<R> X0 = col(rX, y0 - 1), X1 = col(rX, y0), X2 = col(rX, y0 + 1);
-  Col3<R> Y0 = col(rY, y0 - 1), Y1 = col(rY, y0), Y2 = col(rY, y0 + 1);
+  // old rest values of this column, rows y-1 .. y+2
+  R X0, X1, X2, X3, Y0, Y1, Y2, Y3;
+  rest_at(y0 - 1, X0, Y0);
+  rest_at(y0, X1, Y1);
+  rest_at(y0 + 1, X2, Y2);
+  rest_at(y0 + 2, X3, Y3);
   R dc[9], qc[9];
   R phc, psc, sgc, phm, psm, sgm;
-  advance(y0, X0, X1, X2, Y0, Y1, Y2, dc, qc, phc, psc, sgc);
+  load_fg(y0, dc, qc);
+  rebuild(y0, X0, X1, X2, Y0, Y1, Y2, dc, qc, phc, psc, sgc);
   if (walls && y0 == 0) {  // mirror ghost row below the bottom wall
     phm = phc;
     psm = psc;
     sgm = sgc;
   } else {
-    R dt[9], qt[9];
-    const Col3<R> Xa = col(rX, y0 - 2), Ya = col(rY, y0 - 2);
-    advance(y0 == 0 ? ny - 1 : y0 - 1, Xa, X0, X1, Ya, Y0, Y1, dt, qt, phm, psm, sgm);
+    R dt[9], qt[9], Xa, Ya;
+    const int ym = y0 == 0 ? ny - 1 : y0 - 1;
+    rest_at(y0 - 2, Xa, Ya);
+    load_fg(ym, dt, qt);
+    rebuild(ym, Xa, X0, X1, Ya, Y0, Y1, dt, qt, phm, psm, sgm);
   }
-  // window of old rest values: rows y-1 (X0), y (X1), y+1 (X2)
+
+  // software pipeline: the loads for iteration y are issued in iteration
+  // y-1, before its arithmetic and stores
+  R dn[9], qn[9];  // raw deviations of row y+1
+  R hr[8];         // h of row y
+  R uxr, uyr, Sxr, Syr;
+  if (!(walls && y0 + 1 == ny)) load_fg(wrap_y(y0 + 1), dn, qn);
+  load_row(y0, hr, uxr, uyr, Sxr, Syr);
 
   for (int y = y0; y < y1; ++y) {
-    const Col3<R> X3 = col(rX, y + 2), Y3 = col(rY, y + 2);
-    // next row: its deviations are kept for the next iteration
-    R dn[9], qn[9];
+    // rebuild the next row from the raw deviations loaded last iteration
     R phn, psn, sgn;
     const bool ghost = walls && y + 1 == ny;
     if (!ghost) {
-      advance(y + 1 == ny ? 0 : y + 1, X1, X2, X3, Y1, Y2, Y3, dn, qn, phn, psn, sgn);
+      rebuild(wrap_y(y + 1), X1, X2, X3, Y1, Y2, Y3, dn, qn, phn, psn, sgn);
     } else {  // mirror ghost row above the top wall
-#pragma unroll
-      for (int i = 0; i < 9; ++i) dn[i] = qn[i] = R(0);
       phn = phc;
       psn = psc;
       sgn = sgc;
     }
-
-    // current row: h populations and the previous level
-    const RowIdx r = row_index(y, nx, ny, walls);
-    const long long k = r.rc + x;
-    const R php = X1.C, psp = Y1.C;
-    const R uxp = R(aux[k]), uyp = R(aux[pl + k]);
-    R Sxp = R(0), Syp = R(0);
-    if (HAS_S) {
-      Sxp = R(aux[2 * pl + k]);
-      Syp = R(aux[3 * pl + k]);
-    }
     R h[8];
-    pull_h<P>(src, pl, r, x, xm, xp, sc.hi, rho_of(p, php), p.uwb, p.uwt, h);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h[i] = hr[i];
+    const R uxp = uxr, uyp = uyr, Sxp = Sxr, Syp = Syr;
+    R dnn[9], qnn[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      dnn[i] = dn[i];
+      qnn[i] = qn[i];
+    }
+
+    // prefetch for the next iteration
+    R X4 = X3, Y4 = Y3;
+    if (y + 1 < y1) {
+      rest_at(y + 3, X4, Y4);
+      if (!(walls && y + 2 >= ny)) load_fg(wrap_y(y + 2), dn, qn);
+      load_row(y + 1, hr, uxr, uyr, Sxr, Syr);
+    }
+
+    const R php = X1, psp = Y1;
+    const bool bot = walls && y == 0, top = walls && y == ny - 1;
+    wall_terms(bot, top, rho_of(p, php), p.uwb, p.uwt, h);
 
     // stencils from the register window
     const Nine<R> vphi = window(phm, phc, phn);
@@ -375,21 +753,20 @@ lbm_step_kernel(const StepArgs<P> a) {
     collide_site<R, GENR>(p, s, dc, qc, h);
 
     if (interior) {
+      const unsigned rcs = unsigned(y) * rows_s;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        st<P>(dst, i * pl + k, dc[i], sc.f);
-        st<P>(dst, (9 + i) * pl + k, qc[i], sc.g);
+        if constexpr (P::SCALED)
+          PairIO<S>::store(S(dc[i] * sc.f), S(qc[i] * sc.g), rdst, co.p0,
+                           rcs + unsigned(i) * nxb);
+        else
+          PairIO<S>::store(S(dc[i]), S(qc[i]), rdst, co.p0, rcs + unsigned(i) * nxb);
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) st<P>(dst, (18 + i) * pl + k, h[i], sc.h);
-      a.dst_rest[k] = A(phc);
-      a.dst_rest[pl + k] = A(psc);
-      aux[k] = A(s.ux);
-      aux[pl + k] = A(s.uy);
-      if (HAS_S) {
-        aux[2 * pl + k] = A(s.Sx);
-        aux[3 * pl + k] = A(s.Sy);
-      }
+      for (int i = 0; i < 8; ++i) bst<P>(h[i], rdst, co.h0, rcs + hb + unsigned(i) * nxh, sc.h);
+      PairIO<A>::store(A(phc), A(psc), rdrest, brest, unsigned(y) * rrow);
+      PairIO<A>::store(A(s.ux), A(s.uy), raux, baux, unsigned(y) * arow);
+      if (HAS_S) PairIO<A>::store(A(s.Sx), A(s.Sy), raux, baux + 2 * EA, unsigned(y) * arow);
       if (!isfinite(phc + psc + s.ux + s.uy)) *a.flag = 1;
     }
 
@@ -402,15 +779,17 @@ lbm_step_kernel(const StepArgs<P> a) {
     sgc = sgn;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      dc[i] = dn[i];
-      qc[i] = qn[i];
+      dc[i] = dnn[i];
+      qc[i] = qnn[i];
     }
     X0 = X1;
     X1 = X2;
     X2 = X3;
+    X3 = X4;
     Y0 = Y1;
     Y1 = Y2;
     Y2 = Y3;
+    Y3 = Y4;
   }
 }
 
@@ -418,31 +797,37 @@ lbm_step_kernel(const StepArgs<P> a) {
 
 // Neighbour of site (x, y) at offset (dx, dy) in {-1,0,1}^2: periodic in x;
 // periodic in y or, between walls, the wall row itself (mirror ghost).
-__device__ __forceinline__ long long nbr_index(int x, int y, int dx, int dy, int nx,
-                                               int ny, int walls) {
-  int xx = x + dx, yy = y + dy;
+__device__ __forceinline__ void nbr_xy(int x, int y, int dx, int dy, int nx, int ny,
+                                       int walls, int &xx, int &yy) {
+  xx = x + dx;
+  yy = y + dy;
   xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
   if (walls) {
     yy = yy < 0 ? 0 : (yy >= ny ? ny - 1 : yy);
   } else {
     yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
   }
-  return (long long)yy * nx + xx;
 }
 
-template <class T, class R>
-__device__ __forceinline__ Nine<R> gather9(const T *a, int x, int y, int nx, int ny,
-                                           int walls) {
+// The 9-point neighbourhood of site (x, y) of a field given by an index
+// function idx(y, x).
+template <class R, class F>
+__device__ __forceinline__ Nine<R> gather9(F get, int x, int y, int nx, int ny, int walls) {
+  auto v9 = [&](int dx, int dy) {
+    int xx, yy;
+    nbr_xy(x, y, dx, dy, nx, ny, walls, xx, yy);
+    return R(get(yy, xx));
+  };
   Nine<R> v;
-  v.mL = R(a[nbr_index(x, y, -1, -1, nx, ny, walls)]);
-  v.m = R(a[nbr_index(x, y, 0, -1, nx, ny, walls)]);
-  v.mR = R(a[nbr_index(x, y, 1, -1, nx, ny, walls)]);
-  v.cL = R(a[nbr_index(x, y, -1, 0, nx, ny, walls)]);
-  v.c = R(a[nbr_index(x, y, 0, 0, nx, ny, walls)]);
-  v.cR = R(a[nbr_index(x, y, 1, 0, nx, ny, walls)]);
-  v.nL = R(a[nbr_index(x, y, -1, 1, nx, ny, walls)]);
-  v.n = R(a[nbr_index(x, y, 0, 1, nx, ny, walls)]);
-  v.nR = R(a[nbr_index(x, y, 1, 1, nx, ny, walls)]);
+  v.mL = v9(-1, -1);
+  v.m = v9(0, -1);
+  v.mR = v9(1, -1);
+  v.cL = v9(-1, 0);
+  v.c = v9(0, 0);
+  v.cR = v9(1, 0);
+  v.nL = v9(-1, 1);
+  v.n = v9(0, 1);
+  v.nR = v9(1, 1);
   return v;
 }
 
@@ -473,11 +858,13 @@ lbm_init_kernel(const SiteArgs<P> a, const Phys<double> p) {
   const long long n = (long long)a.nx * a.ny;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const int x = int(k % a.nx), y = int(k / a.nx);
+  const int nx = a.nx;
+  const int x = int(k % nx), y = int(k / nx);
   const long long pl = a.plane;
   const double *phi0 = a.scratch, *psi0 = a.scratch + pl;
   const double *ux0 = a.scratch + 2 * pl, *uy0 = a.scratch + 3 * pl;
-  const Nine<double> v = gather9<double, double>(phi0, x, y, a.nx, a.ny, a.walls);
+  const Nine<double> v = gather9<double>([&](int yy, int xx) { return phi0[(long long)yy * nx + xx]; },
+                                         x, y, nx, a.ny, a.walls);
   double gx, gy;
   grad9(v, gx, gy);
   const double phi = phi0[k], psi = psi0[k], ux = ux0[k], uy = uy0[k];
@@ -496,21 +883,23 @@ lbm_init_kernel(const SiteArgs<P> a, const Phys<double> p) {
   const double phis = double(A(phi)), psis = double(A(psi));
   for (int i = 0; i < 9; ++i) {
     const double cu = cx[i] * ux + cy[i] * uy;
-    st<P>(a.dst, i * pl + k, R(w[i] * (phi - phis) + w[i] * phi * 3.0 * cu), a.sc.f);
-    st<P>(a.dst, (9 + i) * pl + k, R(w[i] * (psi - psis) + w[i] * psi * 3.0 * cu), a.sc.g);
+    st<P>(a.dst, fg_idx(i, 0, y, x, nx), R(w[i] * (phi - phis) + w[i] * phi * 3.0 * cu),
+          a.sc.f);
+    st<P>(a.dst, fg_idx(i, 1, y, x, nx), R(w[i] * (psi - psis) + w[i] * psi * 3.0 * cu),
+          a.sc.g);
     if (i > 0) {
       const double cj = cx[i] * jx + cy[i] * jy;
       const double cA = cx[i] * Ax + cy[i] * Ay;
-      st<P>(a.dst, (17 + i) * pl + k, R(w[i] * (3.0 * cj + 4.5 * cA * cu - 1.5 * Au)),
+      st<P>(a.dst, h_idx(i, y, x, nx), R(w[i] * (3.0 * cj + 4.5 * cA * cu - 1.5 * Au)),
             a.sc.h);
     }
   }
-  a.dst_rest[k] = A(phi);
-  a.dst_rest[pl + k] = A(psi);
-  a.aux[k] = A(ux);
-  a.aux[pl + k] = A(uy);
-  a.aux[2 * pl + k] = A(Sx);
-  a.aux[3 * pl + k] = A(Sy);
+  a.dst_rest[rest_idx(0, y, x, nx)] = A(phi);
+  a.dst_rest[rest_idx(1, y, x, nx)] = A(psi);
+  a.aux[aux_idx(0, y, x, nx)] = A(ux);
+  a.aux[aux_idx(1, y, x, nx)] = A(uy);
+  a.aux[aux_idx(2, y, x, nx)] = A(Sx);
+  a.aux[aux_idx(3, y, x, nx)] = A(Sy);
 }
 
 // Read-back, pass 1: phi, psi, sigma of the current level into scratch
@@ -522,17 +911,20 @@ lbm_macro_scalars_kernel(const SiteArgs<P> a, const Phys<typename P::R> p) {
   const long long n = (long long)a.nx * a.ny;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const int x = int(k % a.nx), y = int(k / a.nx);
-  const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
+  const int nx = a.nx;
+  const int x = int(k % nx), y = int(k / nx);
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
   const long long pl = a.plane;
-  const RowIdx r = row_index(y, a.nx, a.ny, a.walls);
+  const RowN r = row_numbers(y, a.ny, a.walls);
   R d[9], q[9], e[9];
-  pull9<P>(a.src, pl, r, x, xm, xp, a.sc.fi, d);
-  pull9<P>(a.src + 9 * pl, pl, r, x, xm, xp, a.sc.gi, q);
-  const Nine<R> vx = gather9<typename P::A, R>(a.src_rest, x, y, a.nx, a.ny, a.walls);
+  pull_fg<P>(a.src, r, x, xm, xp, nx, a.sc.fi, a.sc.gi, d, q);
+  const auto *rs = a.src_rest;
+  const Nine<R> vx = gather9<R>([&](int yy, int xx) { return rs[rest_idx(0, yy, xx, nx)]; },
+                                x, y, nx, a.ny, a.walls);
   source_offsets(vx, r.bot, r.top, e);
   const R phi = restream(d, e, vx.c);
-  const Nine<R> vy = gather9<typename P::A, R>(a.src_rest + pl, x, y, a.nx, a.ny, a.walls);
+  const Nine<R> vy = gather9<R>([&](int yy, int xx) { return rs[rest_idx(1, yy, xx, nx)]; },
+                                x, y, nx, a.ny, a.walls);
   source_offsets(vy, r.bot, r.top, e);
   const R psi = restream(q, e, vy.c);
   R *out = reinterpret_cast<R *>(a.scratch + 5 * pl);
@@ -550,23 +942,28 @@ lbm_macro_fields_kernel(const SiteArgs<P> a, const Phys<typename P::R> p) {
   const long long n = (long long)a.nx * a.ny;
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  const int x = int(k % a.nx), y = int(k / a.nx);
-  const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
+  const int nx = a.nx;
+  const int x = int(k % nx), y = int(k / nx);
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
   const long long pl = a.plane;
   const R *sc = reinterpret_cast<const R *>(a.scratch + 5 * pl);
-  const Nine<R> vphi = gather9<R, R>(sc, x, y, a.nx, a.ny, a.walls);
-  const Nine<R> vsig = gather9<R, R>(sc + 2 * pl, x, y, a.nx, a.ny, a.walls);
+  const Nine<R> vphi = gather9<R>([&](int yy, int xx) { return sc[(long long)yy * nx + xx]; },
+                                  x, y, nx, a.ny, a.walls);
+  const R *ss = sc + 2 * pl;
+  const Nine<R> vsig = gather9<R>([&](int yy, int xx) { return ss[(long long)yy * nx + xx]; },
+                                  x, y, nx, a.ny, a.walls);
   R gfx, gfy, gsx, gsy;
   grad9(vphi, gfx, gfy);
   grad9(vsig, gsx, gsy);
   const R lphi = lap9(vphi);
-  const R php = R(a.src_rest[k]), psp = R(a.src_rest[pl + k]);
-  const R uxp = R(a.aux[k]), uyp = R(a.aux[pl + k]);
-  const R Sxp = HAS_S ? R(a.aux[2 * pl + k]) : R(0);
-  const R Syp = HAS_S ? R(a.aux[3 * pl + k]) : R(0);
-  const RowIdx r = row_index(y, a.nx, a.ny, a.walls);
+  const R php = R(a.src_rest[rest_idx(0, y, x, nx)]);
+  const R psp = R(a.src_rest[rest_idx(1, y, x, nx)]);
+  const R uxp = R(a.aux[aux_idx(0, y, x, nx)]), uyp = R(a.aux[aux_idx(1, y, x, nx)]);
+  const R Sxp = HAS_S ? R(a.aux[aux_idx(2, y, x, nx)]) : R(0);
+  const R Syp = HAS_S ? R(a.aux[aux_idx(3, y, x, nx)]) : R(0);
+  const RowN r = row_numbers(y, a.ny, a.walls);
   R h[8];
-  pull_h<P>(a.src, pl, r, x, xm, xp, a.sc.hi, rho_of(p, php), p.uwb, p.uwt, h);
+  pull_h<P>(a.src, r, x, xm, xp, nx, a.sc.hi, rho_of(p, php), p.uwb, p.uwt, h);
   Front<R> s;
   site_front<R, HAS_S>(p, s, vphi.c, sc[pl + k], vsig.c, gfx, gfy, lphi, gsx, gsy, h, php,
                        psp, uxp, uyp, Sxp, Syp);
@@ -654,9 +1051,9 @@ Layout make_layout(const lbm_params &p) {
   Layout L;
   const long long n = (long long)p.nx * p.ny;
   L.plane = (long long)align_up((size_t)n, 64);
-  L.pop_bytes = align_up((size_t)kPlanes * L.plane * storage_size(p.precision), 256);
-  L.rest_bytes = align_up((size_t)kRest * L.plane * field_size(p.precision), 256);
-  L.aux_bytes = align_up((size_t)kAux * L.plane * field_size(p.precision), 256);
+  L.pop_bytes = align_up((size_t)kPlanes * n * storage_size(p.precision), 256);
+  L.rest_bytes = align_up((size_t)kRest * n * field_size(p.precision), 256);
+  L.aux_bytes = align_up((size_t)kAux * n * field_size(p.precision), 256);
   L.scratch_bytes = align_up((size_t)kScratch * L.plane * 8, 256);
   L.partial_bytes = align_up((size_t)(kReduceBlocks + 1) * kReduceVals * 8, 256);
   size_t o = 0;
@@ -689,6 +1086,13 @@ const char *validate(const lbm_params *p) {
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32 && p->precision != LBM_FP16DEV)
     return "unknown precision";
   if (p->reserved != 0) return "reserved must be 0";
+  {
+    // the step kernel addresses each population copy through one buffer
+    // resource with 32-bit byte offsets
+    const unsigned long long sites = (unsigned long long)p->nx * p->ny;
+    if (kPlanes * sites * storage_size(p->precision) > 0xFFFFFFFFull)
+      return "grid too large: 26 population planes must fit in 4 GiB";
+  }
   if (!(p->phiA > p->phiB)) return "phiA must exceed phiB";
   if (!(p->W > 0)) return "W must be > 0";
   if (!(p->M > 0) || !(p->D > 0)) return "M and D must be > 0 (tau > 1/2)";
@@ -833,7 +1237,7 @@ SiteArgs<P> site_args(lbm_handle *h) {
 }
 
 int default_rows(const lbm_params &p) {
-  const long long strips = (p.nx + kStrip - 1) / kStrip;
+  const long long strips = (p.nx + kCols - 1) / kCols;
   // aim for at least ~8192 wavefronts on large grids, but keep tiles tall
   // enough that the two extra halo rows stay a small overhead
   long long rows = strips * p.ny / 8192;
@@ -853,11 +1257,10 @@ hipError_t launch_step(lbm_handle *h) {
   a.dst_rest = static_cast<typename P::A *>(rest(h, h->cur ^ 1));
   a.aux = static_cast<typename P::A *>(auxp(h));
   a.flag = flagp(h);
-  a.plane = h->L.plane;
   a.nx = h->p.nx;
   a.ny = h->p.ny;
   a.walls = h->p.walls_y;
-  a.nstrips = (h->p.nx + kStrip - 1) / kStrip;
+  a.nstrips = (h->p.nx + kCols - 1) / kCols;
   a.rows = h->rows;
   a.ntiles = a.nstrips * ((h->p.ny + a.rows - 1) / a.rows);
   const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
