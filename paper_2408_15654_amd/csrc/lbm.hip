@@ -57,23 +57,40 @@ constexpr int kReduceVals = 8;
 
 // Storage precisions: S population type, A type of phi/psi/u/S planes,
 // R arithmetic type, SCALED: populations carry power-of-two scales.
+// Minimum waves per SIMD the compiler schedules the step kernel for.  The
+// value steers the instruction scheduler as much as the register budget:
+// measured on the 2048x2048 many-drop field, 1 (no constraint) is best for
+// float64 and float32 storage, 3 for float16 storage, and 4 spills.
+#ifndef LBM_WAVES_F64
+#define LBM_WAVES_F64 1
+#endif
+#ifndef LBM_WAVES_F32
+#define LBM_WAVES_F32 1
+#endif
+#ifndef LBM_WAVES_F16
+#define LBM_WAVES_F16 3
+#endif
+
 struct F64 {
   using S = double;
   using A = double;
   using R = double;
   static constexpr bool SCALED = false;
+  static constexpr int kMinWaves = LBM_WAVES_F64;  // step kernel waves per SIMD
 };
 struct F32 {
   using S = float;
   using A = float;
   using R = float;
   static constexpr bool SCALED = false;
+  static constexpr int kMinWaves = LBM_WAVES_F32;  // step kernel waves per SIMD
 };
 struct F16 {
   using S = _Float16;
   using A = float;
   using R = float;
   static constexpr bool SCALED = true;
+  static constexpr int kMinWaves = LBM_WAVES_F16;  // step kernel waves per SIMD
 };
 
 template <class P>
@@ -499,55 +516,39 @@ struct Pull {
         g[i] = R(b);
       }
     };
+    // One load per population on every path: at a wall row the source of
+    // the three populations leaving through the wall is selected (uniform
+    // over the wavefront), not branched to, so every row issues the same
+    // sequence of memory operations.
+    const bool bot = r.bot, top = r.top;
     pair(0, r.c, c.p0, 0);
     pair(1, r.c, c.pm, 1);
     pair(3, r.c, c.pp, 3);
-    if (r.bot) {
-      pair(4, r.c, c.p0, 2);
-      pair(7, r.c, c.p0, 5);
-      pair(8, r.c, c.p0, 6);
-    } else {
-      pair(2, r.m, c.p0, 2);
-      pair(5, r.m, c.pm, 5);
-      pair(6, r.m, c.pp, 6);
-    }
-    if (r.top) {
-      pair(2, r.c, c.p0, 4);
-      pair(5, r.c, c.p0, 7);
-      pair(6, r.c, c.p0, 8);
-    } else {
-      pair(4, r.p, c.p0, 4);
-      pair(7, r.p, c.pp, 7);
-      pair(8, r.p, c.pm, 8);
-    }
+    pair(0, bot ? r.c + 4 * nxb : r.m + 2 * nxb, c.p0, 2);
+    pair(0, bot ? r.c + 7 * nxb : r.m + 5 * nxb, bot ? c.p0 : c.pm, 5);
+    pair(0, bot ? r.c + 8 * nxb : r.m + 6 * nxb, bot ? c.p0 : c.pp, 6);
+    pair(0, top ? r.c + 2 * nxb : r.p + 4 * nxb, c.p0, 4);
+    pair(0, top ? r.c + 5 * nxb : r.p + 7 * nxb, top ? c.p0 : c.pp, 7);
+    pair(0, top ? r.c + 6 * nxb : r.p + 8 * nxb, top ? c.p0 : c.pm, 8);
   }
   // h_1..h_8 arriving at row r (h[k] = h_{k+1}); hb: byte offset of the H
   // block in a row, nxh: bytes of one h row
   static __device__ __forceinline__ void h(rsrc_t rs, unsigned hb, unsigned nxh,
                                            const RowOff &r, const ColOff &c, R inv, R *out) {
-    auto one = [&](int dir, unsigned row, unsigned col, int k) {
-      out[k] = bld<P>(rs, col, row + hb + unsigned(dir - 1) * nxh, inv);
+    // off: byte offset of the source row and direction plane within the
+    // H block; wall rows select their bounced source as in fg()
+    auto one = [&](unsigned off, unsigned col, int k) {
+      out[k] = bld<P>(rs, col, off + hb, inv);
     };
-    one(1, r.c, c.hm, 0);
-    one(3, r.c, c.hp, 2);
-    if (r.bot) {
-      one(4, r.c, c.h0, 1);
-      one(7, r.c, c.h0, 4);
-      one(8, r.c, c.h0, 5);
-    } else {
-      one(2, r.m, c.h0, 1);
-      one(5, r.m, c.hm, 4);
-      one(6, r.m, c.hp, 5);
-    }
-    if (r.top) {
-      one(2, r.c, c.h0, 3);
-      one(5, r.c, c.h0, 6);
-      one(6, r.c, c.h0, 7);
-    } else {
-      one(4, r.p, c.h0, 3);
-      one(7, r.p, c.hp, 6);
-      one(8, r.p, c.hm, 7);
-    }
+    const bool bot = r.bot, top = r.top;
+    one(r.c, c.hm, 0);             // h_1 from x-1
+    one(r.c + 2 * nxh, c.hp, 2);   // h_3 from x+1
+    one(bot ? r.c + 3 * nxh : r.m + nxh, c.h0, 1);                    // h_2
+    one(bot ? r.c + 6 * nxh : r.m + 4 * nxh, bot ? c.h0 : c.hm, 4);   // h_5
+    one(bot ? r.c + 7 * nxh : r.m + 5 * nxh, bot ? c.h0 : c.hp, 5);   // h_6
+    one(top ? r.c + nxh : r.p + 3 * nxh, c.h0, 3);                    // h_4
+    one(top ? r.c + 4 * nxh : r.p + 6 * nxh, top ? c.h0 : c.hp, 6);   // h_7
+    one(top ? r.c + 5 * nxh : r.p + 7 * nxh, top ? c.h0 : c.hm, 7);   // h_8
   }
 };
 
@@ -570,6 +571,26 @@ __device__ __forceinline__ void wall_terms(bool bot, bool top, R rho_w, R uwb, R
 constexpr int kHalo = 2;                  // halo lanes on each side
 constexpr int kCols = kWave - 2 * kHalo;  // interior columns per wavefront
 
+template <bool B>
+struct BoolC {
+  static constexpr bool value = B;
+};
+
+// v on lanes where own is set, lane kHalo's v elsewhere (lane kHalo is an
+// interior lane of every strip).
+__device__ __forceinline__ unsigned lane_pick(bool own, unsigned v) {
+  const unsigned o = __builtin_amdgcn_readlane(v, kHalo);
+  return own ? v : o;
+}
+__device__ __forceinline__ float lane_pick(bool own, float v) {
+  return __uint_as_float(lane_pick(own, __float_as_uint(v)));
+}
+__device__ __forceinline__ double lane_pick(bool own, double v) {
+  const unsigned lo = lane_pick(own, unsigned(__double2loint(v)));
+  const unsigned hi = lane_pick(own, unsigned(__double2hiint(v)));
+  return __hiloint2double(int(hi), int(lo));
+}
+
 // The fused step: pull-stream + boundaries, phi/psi/sigma, stencils, forces,
 // closures, three MRT collisions, store.  Lanes 0-1 and w+2, w+3 are halo
 // columns: they rebuild phi, psi, sigma for the stencils of the interior
@@ -578,7 +599,7 @@ constexpr int kCols = kWave - 2 * kHalo;  // interior columns per wavefront
 // The row loop is software-pipelined: the loads for row y+1 are issued
 // before the arithmetic and stores of row y.
 template <class P, bool GENR, bool HAS_S>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
 lbm_step_kernel(const StepArgs<P> a) {
   using R = typename P::R;
   using S = typename P::S;
@@ -589,9 +610,9 @@ lbm_step_kernel(const StepArgs<P> a) {
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int tile = blockIdx.x * kWavesPerBlock + wave;
   if (tile >= a.ntiles) return;  // whole wavefronts only
-  const int nx = a.nx, ny = a.ny, walls = a.walls;
   const int strip = tile % a.nstrips;
   const int chunk = tile / a.nstrips;
+  const int nx = a.nx, ny = a.ny, walls = a.walls;
   const int x0 = strip * kCols;
   const int w = min(kCols, nx - x0);
   const bool interior = lane >= kHalo && lane < kHalo + w;
@@ -691,15 +712,27 @@ lbm_step_kernel(const StepArgs<P> a) {
     rebuild(ym, Xa, X0, X1, Ya, Y0, Y1, dt, qt, phm, psm, sgm);
   }
 
-  // software pipeline: the loads for iteration y are issued in iteration
-  // y-1, before its arithmetic and stores
+  // Software pipeline: the loads for row y+1 are issued before the
+  // arithmetic and stores of row y.  Every iteration issues the same
+  // memory operations on every path (no divergent or row-dependent branch
+  // around a load or store), so the wait at the top of an iteration only
+  // covers the loads it needs, not the stores just issued.
   R dn[9], qn[9];  // raw deviations of row y+1
   R hr[8];         // h of row y
   R uxr, uyr, Sxr, Syr;
-  if (!(walls && y0 + 1 == ny)) load_fg(wrap_y(y0 + 1), dn, qn);
+  // above the top wall the next row is the mirror ghost: the load of row
+  // ny-1 keeps the sequence uniform and its values are not used
+  auto next_fg_row = [&](int y) { return (walls && y >= ny) ? ny - 1 : wrap_y(y); };
+  load_fg(next_fg_row(y0 + 1), dn, qn);
   load_row(y0, hr, uxr, uyr, Sxr, Syr);
 
-  for (int y = y0; y < y1; ++y) {
+  // Stores are issued by every lane: a halo lane repeats lane kHalo's value
+  // at lane kHalo's address (identical bits, same cache line).
+  const ColOff cs = {lane_pick(interior, co.p0), 0u, 0u, lane_pick(interior, co.h0), 0u, 0u};
+  const unsigned brest_s = lane_pick(interior, brest), baux_s = lane_pick(interior, baux);
+  bool bad = false;
+
+  auto row_step = [&](int y, auto prefetch) {
     // rebuild the next row from the raw deviations loaded last iteration
     R phn, psn, sgn;
     const bool ghost = walls && y + 1 == ny;
@@ -721,11 +754,10 @@ lbm_step_kernel(const StepArgs<P> a) {
       qnn[i] = qn[i];
     }
 
-    // prefetch for the next iteration
     R X4 = X3, Y4 = Y3;
-    if (y + 1 < y1) {
+    if constexpr (decltype(prefetch)::value) {
       rest_at(y + 3, X4, Y4);
-      if (!(walls && y + 2 >= ny)) load_fg(wrap_y(y + 2), dn, qn);
+      load_fg(next_fg_row(y + 2), dn, qn);
       load_row(y + 1, hr, uxr, uyr, Sxr, Syr);
     }
 
@@ -752,23 +784,26 @@ lbm_step_kernel(const StepArgs<P> a) {
     }
     collide_site<R, GENR>(p, s, dc, qc, h);
 
-    if (interior) {
-      const unsigned rcs = unsigned(y) * rows_s;
+    const unsigned rcs = unsigned(y) * rows_s;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        if constexpr (P::SCALED)
-          PairIO<S>::store(S(dc[i] * sc.f), S(qc[i] * sc.g), rdst, co.p0,
-                           rcs + unsigned(i) * nxb);
-        else
-          PairIO<S>::store(S(dc[i]), S(qc[i]), rdst, co.p0, rcs + unsigned(i) * nxb);
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) bst<P>(h[i], rdst, co.h0, rcs + hb + unsigned(i) * nxh, sc.h);
-      PairIO<A>::store(A(phc), A(psc), rdrest, brest, unsigned(y) * rrow);
-      PairIO<A>::store(A(s.ux), A(s.uy), raux, baux, unsigned(y) * arow);
-      if (HAS_S) PairIO<A>::store(A(s.Sx), A(s.Sy), raux, baux + 2 * EA, unsigned(y) * arow);
-      if (!isfinite(phc + psc + s.ux + s.uy)) *a.flag = 1;
+    for (int i = 0; i < 9; ++i) {
+      const R a = lane_pick(interior, dc[i]), b = lane_pick(interior, qc[i]);
+      if constexpr (P::SCALED)
+        PairIO<S>::store(S(a * sc.f), S(b * sc.g), rdst, cs.p0, rcs + unsigned(i) * nxb);
+      else
+        PairIO<S>::store(S(a), S(b), rdst, cs.p0, rcs + unsigned(i) * nxb);
     }
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      bst<P>(lane_pick(interior, h[i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh, sc.h);
+    PairIO<A>::store(A(lane_pick(interior, phc)), A(lane_pick(interior, psc)), rdrest,
+                     brest_s, unsigned(y) * rrow);
+    PairIO<A>::store(A(lane_pick(interior, s.ux)), A(lane_pick(interior, s.uy)), raux, baux_s,
+                     unsigned(y) * arow);
+    if (HAS_S)
+      PairIO<A>::store(A(lane_pick(interior, s.Sx)), A(lane_pick(interior, s.Sy)), raux,
+                       baux_s + 2 * EA, unsigned(y) * arow);
+    bad |= interior && !isfinite(phc + psc + s.ux + s.uy);
 
     // slide the windows
     phm = phc;
@@ -790,7 +825,11 @@ lbm_step_kernel(const StepArgs<P> a) {
     Y1 = Y2;
     Y2 = Y3;
     Y3 = Y4;
-  }
+  };
+
+  for (int y = y0; y < y1 - 1; ++y) row_step(y, BoolC<true>{});
+  row_step(y1 - 1, BoolC<false>{});  // the last row prefetches nothing
+  if (bad) *a.flag = 1;
 }
 
 // ------------------------------------------------------------ site kernels
@@ -1238,10 +1277,13 @@ SiteArgs<P> site_args(lbm_handle *h) {
 
 int default_rows(const lbm_params &p) {
   const long long strips = (p.nx + kCols - 1) / kCols;
-  // aim for at least ~8192 wavefronts on large grids, but keep tiles tall
-  // enough that the two extra halo rows stay a small overhead
-  long long rows = strips * p.ny / 8192;
-  if (rows < 8) rows = 8;
+  // Many short tiles keep the wavefronts' start-up and drain phases
+  // staggered; the two extra halo rows per tile are served mostly from
+  // cache.  Measured on 2048x2048: 4 rows for float32/float16 storage,
+  // about 12 for float64 (fewer resident waves, longer rows).
+  const long long target = p.precision == LBM_FP64 ? 6144 : 16384;
+  long long rows = strips * p.ny / target;
+  if (rows < 4) rows = 4;
   if (rows > 64) rows = 64;
   return int(rows);
 }
