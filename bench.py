@@ -31,10 +31,14 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "lbm_step_kernel_many_drops_2048_
 
 def algorithmic_bytes_per_site(precision: str, has_s: bool) -> int:
     """Bytes one site-update must move: 26 live populations read and written
-    (f_0..f_8, g_0..g_8, h_1..h_8) plus the previous level (phi, psi, ux,
-    uy and, with a density contrast, Sx, Sy) read and written."""
-    aux = 6 if has_s else 4
-    return 2 * 26 * STORE_BYTES[precision] + 2 * aux * FIELD_BYTES[precision]
+    (f_0..f_8, g_0..g_8, h_1..h_8) plus the previous level read and written.
+    float64/float32 storage keep (phi, psi) as rest values and (ux, uy) and,
+    with a density contrast, (Sx, Sy) as aux; float16 storage keeps
+    (phi, psi, P, rho ux, rho uy) in float32 as rest values (the bases of the
+    stored deviations) and (Sx, Sy) as aux."""
+    s = 2 if has_s else 0
+    fields = 5 + s if precision == "fp16dev" else 4 + s
+    return 2 * 26 * STORE_BYTES[precision] + 2 * fields * FIELD_BYTES[precision]
 
 
 def kernel_source_hash() -> str:

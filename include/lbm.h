@@ -53,9 +53,11 @@ typedef enum {
 
 /* Storage precision of the populations.  LBM_FP64: float64 storage and
  * arithmetic.  LBM_FP32: float32 storage and arithmetic.  LBM_FP16DEV: each
- * population stored as a float16 deviation from its rest equilibrium
- * (w_i phi for f, w_i psi for g, 0 for h), scaled by a power of two, with
- * float32 arithmetic. */
+ * population stored as a float16 deviation, scaled by a power of two, with
+ * float32 arithmetic and float32 phi, psi: f_i - w_i phi and g_i - w_i psi
+ * (the rest equilibria of Eqs. (22), (26)), and h_i - 3 w_i (P + c_i . rho u)
+ * (the part of Eq. (30) linear in P and rho u), each relative to the stored
+ * values of the site that wrote it. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16DEV = 2 } lbm_precision;
 
 /* Equation of state sigma(psi): linear Eq. (20) or Langmuir Eq. (19). */

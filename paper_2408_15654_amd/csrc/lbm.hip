@@ -49,18 +49,15 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kPlanes = 26;
-constexpr int kRest = 2;
-constexpr int kAux = 4;
 constexpr int kScratch = 8;
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceVals = 8;
 
-// Storage precisions: S population type, A type of phi/psi/u/S planes,
-// R arithmetic type, SCALED: populations carry power-of-two scales.
 // Minimum waves per SIMD the compiler schedules the step kernel for.  The
 // value steers the instruction scheduler as much as the register budget:
 // measured on the 2048x2048 many-drop field, 1 (no constraint) is best for
-// float64 and float32 storage, 3 for float16 storage, and 4 spills.
+// float64 and float32 storage, 2 for float16 storage (3 spills), and 4
+// spills for all.
 #ifndef LBM_WAVES_F64
 #define LBM_WAVES_F64 1
 #endif
@@ -68,15 +65,21 @@ constexpr int kReduceVals = 8;
 #define LBM_WAVES_F32 1
 #endif
 #ifndef LBM_WAVES_F16
-#define LBM_WAVES_F16 3
+#define LBM_WAVES_F16 2
 #endif
 
+// Storage precisions: S population type, A type of phi/psi/u/S planes,
+// R arithmetic type, SCALED: populations carry power-of-two scales.
 struct F64 {
   using S = double;
   using A = double;
   using R = double;
   static constexpr bool SCALED = false;
   static constexpr int kMinWaves = LBM_WAVES_F64;  // step kernel waves per SIMD
+  static constexpr bool HDEV = false;  // h stored raw
+  static constexpr int kRest = 2;      // rest record: phi, psi
+  static constexpr int kAux = 4;       // aux record: ux, uy, Sx, Sy
+  static constexpr int kAuxS = 2;      // offset of Sx in the aux record
 };
 struct F32 {
   using S = float;
@@ -84,6 +87,10 @@ struct F32 {
   using R = float;
   static constexpr bool SCALED = false;
   static constexpr int kMinWaves = LBM_WAVES_F32;  // step kernel waves per SIMD
+  static constexpr bool HDEV = false;
+  static constexpr int kRest = 2;
+  static constexpr int kAux = 4;
+  static constexpr int kAuxS = 2;
 };
 struct F16 {
   using S = _Float16;
@@ -91,6 +98,13 @@ struct F16 {
   using R = float;
   static constexpr bool SCALED = true;
   static constexpr int kMinWaves = LBM_WAVES_F16;  // step kernel waves per SIMD
+  // h_k stored as deviations from 3 w_k (P + c_k . rho u) of the storing
+  // site; P and rho u join phi, psi in the rest record, and the previous
+  // velocity is rho u / rho(phi) of that record, so aux holds S only.
+  static constexpr bool HDEV = true;
+  static constexpr int kRest = 5;  // rest record: phi, psi, P, rho ux, rho uy
+  static constexpr int kAux = 2;   // aux record: Sx, Sy
+  static constexpr int kAuxS = 0;
 };
 
 template <class P>
@@ -272,11 +286,13 @@ __device__ __forceinline__ long long fg_idx(int i, int c, int y, int x, int nx) 
 __device__ __forceinline__ long long h_idx(int i, int y, int x, int nx) {
   return (long long)y * (kPlanes * nx) + 18LL * nx + (long long)(i - 1) * nx + x;
 }
+template <class P>
 __device__ __forceinline__ long long rest_idx(int c, int y, int x, int nx) {
-  return ((long long)y * nx + x) * kRest + c;
+  return ((long long)y * nx + x) * P::kRest + c;
 }
+template <class P>
 __device__ __forceinline__ long long aux_idx(int c, int y, int x, int nx) {
-  return ((long long)y * nx + x) * kAux + c;
+  return ((long long)y * nx + x) * P::kAux + c;
 }
 
 // Rows y-1, y, y+1 to pull from (valid even at walls) and the wall flags of
@@ -361,6 +377,54 @@ __device__ __forceinline__ void pull_h(const typename P::S *__restrict__ s, cons
 // own value: e_i = X(x - c_i) - X(x); bounced populations come from the
 // site itself (e_i = 0).  v holds X at rows r-1 (m), r (c), r+1 (n) of
 // columns x-1 (L), x, x+1 (R).
+// Rest part of h_k under float16 storage: 3 w_k (P + c_k . j), j = rho u,
+// with (sx, sy) = c_k.  The storing site subtracts it for each outgoing k
+// and the receiving site adds the same expression of the same stored
+// values back, so the two cancel exactly.
+template <class R>
+__device__ __forceinline__ R hb(R w3, R P, int sx, R jx, int sy, R jy) {
+  R t = P;
+  if (sx > 0) t += jx;
+  if (sx < 0) t -= jx;
+  if (sy > 0) t += jy;
+  if (sy < 0) t -= jy;
+  return w3 * t;
+}
+template <class R>
+struct HRest {
+  R P, jx, jy;
+};
+// Rest parts of the post-collision h_1..h_8 stored at one site (b[k] for
+// h_{k+1}).
+template <class R>
+__device__ __forceinline__ void h_store_basis(const HRest<R> &v, R *b) {
+  const R a = R(1) / R(3), d = R(1) / R(12);  // 3 w_k
+  b[0] = hb(a, v.P, 1, v.jx, 0, v.jy);
+  b[1] = hb(a, v.P, 0, v.jx, 1, v.jy);
+  b[2] = hb(a, v.P, -1, v.jx, 0, v.jy);
+  b[3] = hb(a, v.P, 0, v.jx, -1, v.jy);
+  b[4] = hb(d, v.P, 1, v.jx, 1, v.jy);
+  b[5] = hb(d, v.P, -1, v.jx, 1, v.jy);
+  b[6] = hb(d, v.P, -1, v.jx, -1, v.jy);
+  b[7] = hb(d, v.P, 1, v.jx, -1, v.jy);
+}
+// Rest parts of the h_1..h_8 arriving at a site from the 9-point windows
+// of the stored (P, jx, jy): each from its source site x - c_k, or at a
+// wall row from the site itself, where the arriving h_k left as h_-k.
+template <class R>
+__device__ __forceinline__ void h_arrival_basis(const Nine<R> &P, const Nine<R> &jx,
+                                                const Nine<R> &jy, bool bot, bool top, R *b) {
+  const R a = R(1) / R(3), d = R(1) / R(12);
+  b[0] = hb(a, P.cL, 1, jx.cL, 0, jy.cL);
+  b[2] = hb(a, P.cR, -1, jx.cR, 0, jy.cR);
+  b[1] = bot ? hb(a, P.c, 0, jx.c, -1, jy.c) : hb(a, P.m, 0, jx.m, 1, jy.m);
+  b[4] = bot ? hb(d, P.c, -1, jx.c, -1, jy.c) : hb(d, P.mL, 1, jx.mL, 1, jy.mL);
+  b[5] = bot ? hb(d, P.c, 1, jx.c, -1, jy.c) : hb(d, P.mR, -1, jx.mR, 1, jy.mR);
+  b[3] = top ? hb(a, P.c, 0, jx.c, 1, jy.c) : hb(a, P.n, 0, jx.n, -1, jy.n);
+  b[6] = top ? hb(d, P.c, 1, jx.c, 1, jy.c) : hb(d, P.nR, -1, jx.nR, -1, jy.nR);
+  b[7] = top ? hb(d, P.c, -1, jx.c, 1, jy.c) : hb(d, P.nL, 1, jx.nL, -1, jy.nL);
+}
+
 template <class R>
 __device__ __forceinline__ void source_offsets(const Nine<R> &v, bool bot, bool top, R *e) {
   const R c = v.c;
@@ -470,6 +534,27 @@ struct PairIO<_Float16> {
                          hi = __builtin_bit_cast(unsigned short, b);
     const unsigned w = unsigned(lo) | (unsigned(hi) << 16);
     __builtin_amdgcn_raw_buffer_store_b32(w, r, v, s, 0);
+  }
+};
+
+// Three floats through one 96-bit access.
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+struct TripleIO {
+  static __device__ __forceinline__ void load(rsrc_t r, unsigned v, unsigned s, float &a,
+                                              float &b, float &c) {
+    const u32x3 w = __builtin_amdgcn_raw_buffer_load_b96(r, v, s, 0);
+    const unsigned w0 = w[0], w1 = w[1], w2 = w[2];
+    a = __uint_as_float(w0);
+    b = __uint_as_float(w1);
+    c = __uint_as_float(w2);
+  }
+  static __device__ __forceinline__ void store(float a, float b, float c, rsrc_t r, unsigned v,
+                                               unsigned s) {
+    u32x3 w;
+    w[0] = __float_as_uint(a);
+    w[1] = __float_as_uint(b);
+    w[2] = __float_as_uint(c);
+    __builtin_amdgcn_raw_buffer_store_b96(w, r, v, s, 0);
   }
 };
 
@@ -630,8 +715,8 @@ lbm_step_kernel(const StepArgs<P> a) {
   co.h0 = xc * ES;
   co.hm = xcm * ES;
   co.hp = xcp * ES;
-  const unsigned brest = xc * kRest * EA;  // this site's (phi, psi) pair in a row
-  const unsigned baux = xc * kAux * EA;    // this site's (ux, uy, Sx, Sy)
+  const unsigned brest = xc * P::kRest * EA;  // this site's rest record in a row
+  const unsigned baux = xc * P::kAux * EA;    // this site's aux record
   const int y0 = chunk * a.rows;
   const int y1 = min(y0 + a.rows, ny);
   const unsigned nsites = unsigned(nx) * unsigned(ny);
@@ -639,13 +724,13 @@ lbm_step_kernel(const StepArgs<P> a) {
   const unsigned nxh = unsigned(nx) * ES;          // one h row
   const unsigned hb = 9u * nxb;                    // H block offset in a row
   const unsigned rows_s = unsigned(kPlanes) * nxh; // bytes per population row
-  const unsigned rrow = unsigned(nx) * kRest * EA; // bytes per rest row
-  const unsigned arow = unsigned(nx) * kAux * EA;  // bytes per aux row
+  const unsigned rrow = unsigned(nx) * P::kRest * EA; // bytes per rest row
+  const unsigned arow = unsigned(nx) * P::kAux * EA;  // bytes per aux row
   const rsrc_t rsrc = make_rsrc(a.src, unsigned(kPlanes) * nsites * ES);
   const rsrc_t rdst = make_rsrc(a.dst, unsigned(kPlanes) * nsites * ES);
-  const rsrc_t rrest = make_rsrc(a.src_rest, unsigned(kRest) * nsites * EA);
-  const rsrc_t rdrest = make_rsrc(a.dst_rest, unsigned(kRest) * nsites * EA);
-  const rsrc_t raux = make_rsrc(a.aux, unsigned(kAux) * nsites * EA);
+  const rsrc_t rrest = make_rsrc(a.src_rest, unsigned(P::kRest) * nsites * EA);
+  const rsrc_t rdrest = make_rsrc(a.dst_rest, unsigned(P::kRest) * nsites * EA);
+  const rsrc_t raux = make_rsrc(a.aux, unsigned(P::kAux) * nsites * EA);
   const Phys<R> &p = a.p;
   const Scales<P> &sc = a.sc;
 
@@ -664,16 +749,26 @@ lbm_step_kernel(const StepArgs<P> a) {
   auto load_row = [&](int y, R *h, R &uxp, R &uyp, R &Sxp, R &Syp) {
     Pull<P>::h(rsrc, hb, nxh, row_offsets(y, ny, walls, rows_s), co, sc.hi, h);
     A u, v;
-    PairIO<A>::load(raux, baux, unsigned(y) * arow, u, v);
-    uxp = R(u);
-    uyp = R(v);
+    if constexpr (!P::HDEV) {
+      PairIO<A>::load(raux, baux, unsigned(y) * arow, u, v);
+      uxp = R(u);
+      uyp = R(v);
+    } else {  // from the rest record (P, rho u) instead
+      uxp = uyp = R(0);
+    }
     if (HAS_S) {
-      PairIO<A>::load(raux, baux + 2 * EA, unsigned(y) * arow, u, v);
+      PairIO<A>::load(raux, baux + P::kAuxS * EA, unsigned(y) * arow, u, v);
       Sxp = R(u);
       Syp = R(v);
     } else {
       Sxp = Syp = R(0);
     }
+  };
+  // old (P, rho ux, rho uy) of this column at row y (float16 storage only)
+  auto hrest_at = [&](int y, HRest<R> &v) {
+    if constexpr (P::HDEV)
+      TripleIO::load(rrest, brest + 2 * EA, unsigned(wrap_row(y, ny, walls)) * rrow, v.P, v.jx,
+                     v.jy);
   };
   // rebuild row r from its raw deviations: new phi, psi, sigma, and the
   // deviations relative to them (in place), given the old rest fields at
@@ -725,6 +820,13 @@ lbm_step_kernel(const StepArgs<P> a) {
   auto next_fg_row = [&](int y) { return (walls && y >= ny) ? ny - 1 : wrap_y(y); };
   load_fg(next_fg_row(y0 + 1), dn, qn);
   load_row(y0, hr, uxr, uyr, Sxr, Syr);
+  // rest (P, rho u) of rows y-1, y, y+1 and the prefetched y+2
+  HRest<R> Hm{}, Hc{}, Hn{}, Hq{};
+  if constexpr (P::HDEV) {
+    hrest_at(y0 - 1, Hm);
+    hrest_at(y0, Hc);
+    hrest_at(y0 + 1, Hn);
+  }
 
   // Stores are issued by every lane: a halo lane repeats lane kHalo's value
   // at lane kHalo's address (identical bits, same cache line).
@@ -746,7 +848,18 @@ lbm_step_kernel(const StepArgs<P> a) {
     R h[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) h[i] = hr[i];
-    const R uxp = uxr, uyp = uyr, Sxp = Sxr, Syp = Syr;
+    R uxp = uxr, uyp = uyr;
+    const R Sxp = Sxr, Syp = Syr;
+    if constexpr (P::HDEV) {  // add back the rest parts of the arriving h
+      R b[8];
+      h_arrival_basis(window(Hm.P, Hc.P, Hn.P), window(Hm.jx, Hc.jx, Hn.jx),
+                      window(Hm.jy, Hc.jy, Hn.jy), walls && y == 0, walls && y == ny - 1, b);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) h[i] += b[i];
+      const R irho = R(1) / rho_of(p, X1);
+      uxp = Hc.jx * irho;
+      uyp = Hc.jy * irho;
+    }
     R dnn[9], qnn[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -759,6 +872,7 @@ lbm_step_kernel(const StepArgs<P> a) {
       rest_at(y + 3, X4, Y4);
       load_fg(next_fg_row(y + 2), dn, qn);
       load_row(y + 1, hr, uxr, uyr, Sxr, Syr);
+      hrest_at(y + 2, Hq);
     }
 
     const R php = X1, psp = Y1;
@@ -785,24 +899,38 @@ lbm_step_kernel(const StepArgs<P> a) {
     collide_site<R, GENR>(p, s, dc, qc, h);
 
     const unsigned rcs = unsigned(y) * rows_s;
+    if constexpr (P::SCALED) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const R a = lane_pick(interior, dc[i]), b = lane_pick(interior, qc[i]);
-      if constexpr (P::SCALED)
-        PairIO<S>::store(S(a * sc.f), S(b * sc.g), rdst, cs.p0, rcs + unsigned(i) * nxb);
-      else
-        PairIO<S>::store(S(a), S(b), rdst, cs.p0, rcs + unsigned(i) * nxb);
+      for (int i = 0; i < 9; ++i)
+        PairIO<S>::store(S(lane_pick(interior, dc[i]) * sc.f), S(lane_pick(interior, qc[i]) * sc.g),
+                         rdst, cs.p0, rcs + unsigned(i) * nxb);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        PairIO<S>::store(S(lane_pick(interior, dc[i])), S(lane_pick(interior, qc[i])), rdst,
+                         cs.p0, rcs + unsigned(i) * nxb);
+    }
+    if constexpr (P::HDEV) {  // h as deviations from this site's new rest parts
+      const HRest<R> hn = {s.P, s.jx, s.jy};
+      R b[8];
+      h_store_basis(hn, b);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) h[i] -= b[i];
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i)
       bst<P>(lane_pick(interior, h[i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh, sc.h);
     PairIO<A>::store(A(lane_pick(interior, phc)), A(lane_pick(interior, psc)), rdrest,
                      brest_s, unsigned(y) * rrow);
-    PairIO<A>::store(A(lane_pick(interior, s.ux)), A(lane_pick(interior, s.uy)), raux, baux_s,
-                     unsigned(y) * arow);
+    if constexpr (P::HDEV)
+      TripleIO::store(lane_pick(interior, s.P), lane_pick(interior, s.jx),
+                      lane_pick(interior, s.jy), rdrest, brest_s + 2 * EA, unsigned(y) * rrow);
+    else
+      PairIO<A>::store(A(lane_pick(interior, s.ux)), A(lane_pick(interior, s.uy)), raux,
+                       baux_s, unsigned(y) * arow);
     if (HAS_S)
       PairIO<A>::store(A(lane_pick(interior, s.Sx)), A(lane_pick(interior, s.Sy)), raux,
-                       baux_s + 2 * EA, unsigned(y) * arow);
+                       baux_s + P::kAuxS * EA, unsigned(y) * arow);
     bad |= interior && !isfinite(phc + psc + s.ux + s.uy);
 
     // slide the windows
@@ -825,6 +953,11 @@ lbm_step_kernel(const StepArgs<P> a) {
     Y1 = Y2;
     Y2 = Y3;
     Y3 = Y4;
+    if constexpr (P::HDEV) {
+      Hm = Hc;
+      Hc = Hn;
+      Hn = Hq;
+    }
   };
 
   for (int y = y0; y < y1 - 1; ++y) row_step(y, BoolC<true>{});
@@ -920,6 +1053,12 @@ lbm_init_kernel(const SiteArgs<P> a, const Phys<double> p) {
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
   const double phis = double(A(phi)), psis = double(A(psi));
+  // float16 storage: h relative to the rest parts of the STORED (P = 0, rho u)
+  R hbase[8] = {};
+  if constexpr (P::HDEV) {
+    const HRest<R> v = {R(0), R(A(jx)), R(A(jy))};
+    h_store_basis(v, hbase);
+  }
   for (int i = 0; i < 9; ++i) {
     const double cu = cx[i] * ux + cy[i] * uy;
     st<P>(a.dst, fg_idx(i, 0, y, x, nx), R(w[i] * (phi - phis) + w[i] * phi * 3.0 * cu),
@@ -929,16 +1068,22 @@ lbm_init_kernel(const SiteArgs<P> a, const Phys<double> p) {
     if (i > 0) {
       const double cj = cx[i] * jx + cy[i] * jy;
       const double cA = cx[i] * Ax + cy[i] * Ay;
-      st<P>(a.dst, h_idx(i, y, x, nx), R(w[i] * (3.0 * cj + 4.5 * cA * cu - 1.5 * Au)),
-            a.sc.h);
+      st<P>(a.dst, h_idx(i, y, x, nx),
+            R(w[i] * (3.0 * cj + 4.5 * cA * cu - 1.5 * Au) - double(hbase[i - 1])), a.sc.h);
     }
   }
-  a.dst_rest[rest_idx(0, y, x, nx)] = A(phi);
-  a.dst_rest[rest_idx(1, y, x, nx)] = A(psi);
-  a.aux[aux_idx(0, y, x, nx)] = A(ux);
-  a.aux[aux_idx(1, y, x, nx)] = A(uy);
-  a.aux[aux_idx(2, y, x, nx)] = A(Sx);
-  a.aux[aux_idx(3, y, x, nx)] = A(Sy);
+  a.dst_rest[rest_idx<P>(0, y, x, nx)] = A(phi);
+  a.dst_rest[rest_idx<P>(1, y, x, nx)] = A(psi);
+  if constexpr (P::HDEV) {
+    a.dst_rest[rest_idx<P>(2, y, x, nx)] = A(0);
+    a.dst_rest[rest_idx<P>(3, y, x, nx)] = A(jx);
+    a.dst_rest[rest_idx<P>(4, y, x, nx)] = A(jy);
+  } else {
+    a.aux[aux_idx<P>(0, y, x, nx)] = A(ux);
+    a.aux[aux_idx<P>(1, y, x, nx)] = A(uy);
+  }
+  a.aux[aux_idx<P>(P::kAuxS, y, x, nx)] = A(Sx);
+  a.aux[aux_idx<P>(P::kAuxS + 1, y, x, nx)] = A(Sy);
 }
 
 // Read-back, pass 1: phi, psi, sigma of the current level into scratch
@@ -958,11 +1103,11 @@ lbm_macro_scalars_kernel(const SiteArgs<P> a, const Phys<typename P::R> p) {
   R d[9], q[9], e[9];
   pull_fg<P>(a.src, r, x, xm, xp, nx, a.sc.fi, a.sc.gi, d, q);
   const auto *rs = a.src_rest;
-  const Nine<R> vx = gather9<R>([&](int yy, int xx) { return rs[rest_idx(0, yy, xx, nx)]; },
+  const Nine<R> vx = gather9<R>([&](int yy, int xx) { return rs[rest_idx<P>(0, yy, xx, nx)]; },
                                 x, y, nx, a.ny, a.walls);
   source_offsets(vx, r.bot, r.top, e);
   const R phi = restream(d, e, vx.c);
-  const Nine<R> vy = gather9<R>([&](int yy, int xx) { return rs[rest_idx(1, yy, xx, nx)]; },
+  const Nine<R> vy = gather9<R>([&](int yy, int xx) { return rs[rest_idx<P>(1, yy, xx, nx)]; },
                                 x, y, nx, a.ny, a.walls);
   source_offsets(vy, r.bot, r.top, e);
   const R psi = restream(q, e, vy.c);
@@ -995,14 +1140,31 @@ lbm_macro_fields_kernel(const SiteArgs<P> a, const Phys<typename P::R> p) {
   grad9(vphi, gfx, gfy);
   grad9(vsig, gsx, gsy);
   const R lphi = lap9(vphi);
-  const R php = R(a.src_rest[rest_idx(0, y, x, nx)]);
-  const R psp = R(a.src_rest[rest_idx(1, y, x, nx)]);
-  const R uxp = R(a.aux[aux_idx(0, y, x, nx)]), uyp = R(a.aux[aux_idx(1, y, x, nx)]);
-  const R Sxp = HAS_S ? R(a.aux[aux_idx(2, y, x, nx)]) : R(0);
-  const R Syp = HAS_S ? R(a.aux[aux_idx(3, y, x, nx)]) : R(0);
+  const R php = R(a.src_rest[rest_idx<P>(0, y, x, nx)]);
+  const R psp = R(a.src_rest[rest_idx<P>(1, y, x, nx)]);
+  const R Sxp = HAS_S ? R(a.aux[aux_idx<P>(P::kAuxS, y, x, nx)]) : R(0);
+  const R Syp = HAS_S ? R(a.aux[aux_idx<P>(P::kAuxS + 1, y, x, nx)]) : R(0);
   const RowN r = row_numbers(y, a.ny, a.walls);
   R h[8];
   pull_h<P>(a.src, r, x, xm, xp, nx, a.sc.hi, rho_of(p, php), p.uwb, p.uwt, h);
+  R uxp, uyp;
+  if constexpr (P::HDEV) {
+    const auto *rs = a.src_rest;
+    auto g = [&](int c) {
+      return gather9<R>([&](int yy, int xx) { return rs[rest_idx<P>(c, yy, xx, nx)]; }, x, y,
+                        nx, a.ny, a.walls);
+    };
+    const Nine<R> vP = g(2), vjx = g(3), vjy = g(4);
+    R b[8];
+    h_arrival_basis(vP, vjx, vjy, r.bot, r.top, b);
+    for (int i = 0; i < 8; ++i) h[i] += b[i];
+    const R irho = R(1) / rho_of(p, php);
+    uxp = vjx.c * irho;
+    uyp = vjy.c * irho;
+  } else {
+    uxp = R(a.aux[aux_idx<P>(0, y, x, nx)]);
+    uyp = R(a.aux[aux_idx<P>(1, y, x, nx)]);
+  }
   Front<R> s;
   site_front<R, HAS_S>(p, s, vphi.c, sc[pl + k], vsig.c, gfx, gfy, lphi, gsx, gsy, h, php,
                        psp, uxp, uyp, Sxp, Syp);
@@ -1079,6 +1241,9 @@ size_t storage_size(int prec) {
   return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2);
 }
 size_t field_size(int prec) { return prec == LBM_FP64 ? 8 : 4; }
+// fields per site of the rest record (ping-pong) and the aux record
+int rest_fields(int prec) { return prec == LBM_FP16DEV ? F16::kRest : F32::kRest; }
+int aux_fields(int prec) { return prec == LBM_FP16DEV ? F16::kAux : F32::kAux; }
 
 struct Layout {
   long long plane;  // elements per plane
@@ -1091,8 +1256,8 @@ Layout make_layout(const lbm_params &p) {
   const long long n = (long long)p.nx * p.ny;
   L.plane = (long long)align_up((size_t)n, 64);
   L.pop_bytes = align_up((size_t)kPlanes * n * storage_size(p.precision), 256);
-  L.rest_bytes = align_up((size_t)kRest * n * field_size(p.precision), 256);
-  L.aux_bytes = align_up((size_t)kAux * n * field_size(p.precision), 256);
+  L.rest_bytes = align_up((size_t)rest_fields(p.precision) * n * field_size(p.precision), 256);
+  L.aux_bytes = align_up((size_t)aux_fields(p.precision) * n * field_size(p.precision), 256);
   L.scratch_bytes = align_up((size_t)kScratch * L.plane * 8, 256);
   L.partial_bytes = align_up((size_t)(kReduceBlocks + 1) * kReduceVals * 8, 256);
   size_t o = 0;
@@ -1131,6 +1296,8 @@ const char *validate(const lbm_params *p) {
     const unsigned long long sites = (unsigned long long)p->nx * p->ny;
     if (kPlanes * sites * storage_size(p->precision) > 0xFFFFFFFFull)
       return "grid too large: 26 population planes must fit in 4 GiB";
+    if (rest_fields(p->precision) * sites * field_size(p->precision) > 0xFFFFFFFFull)
+      return "grid too large: the rest records must fit in 4 GiB";
   }
   if (!(p->phiA > p->phiB)) return "phiA must exceed phiB";
   if (!(p->W > 0)) return "W must be > 0";
@@ -1202,7 +1369,7 @@ Phys<R> make_phys(const lbm_params &q) {
 // their field, h_i are O(w_i (3P + 3 c.rho u)); the scales put the expected
 // magnitudes near 2^4..2^8, well inside float16's normal range.
 void fp16_scales(const lbm_params &q, double out[3]) {
-  const double dflt[3] = {4096.0, 4096.0, 16384.0};
+  const double dflt[3] = {4096.0, 4096.0, 65536.0};
   for (int a = 0; a < 3; ++a) out[a] = q.fp16_scale[a] > 0 ? q.fp16_scale[a] : dflt[a];
 }
 

@@ -70,6 +70,12 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with "
                           "`python -m paper_2408_15654_amd.build`")
+    # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one
+    # the library binds to.  Loaded the other way round, torch would load a
+    # second runtime under another file name and the two would not share
+    # device memory.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER(lbm_params)
     vp, dp, H = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p
