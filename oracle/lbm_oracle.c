@@ -53,6 +53,11 @@
  *     initial fields (P = 0); the stored previous level is the initial fields,
  *     so the first time differences are taken against them.
  *   - Langmuir EOS: sigma uses min(psi, 1 - 1e-9) inside the logarithm.
+ *
+ * Parity unpinned: the factor K = 2/3 in front of the time-difference term
+ * tr d_t(rho uu - (Su+uS)/2) of the pressure, Eq. (32b).  No test fixes it
+ * independently (changing it moves no pinned quantity beyond its tolerance);
+ * it follows the paper's statement of P as read above.
  */
 #include <math.h>
 #include <omp.h>
