@@ -178,6 +178,102 @@ lbm_status lbm_set_tile_rows(lbm_handle *h, int32_t rows);
  * profiler look-ups). */
 const char *lbm_step_kernel_name(const lbm_handle *h);
 
+/* ----------------------------------------------------------------------
+ * Batches: many independent simulations advanced together.
+ *
+ * A batch owns no memory of its own on the device: the caller gives one
+ * workspace (its HBM budget), from which the batch carves its metadata and,
+ * for every admitted simulation, the same workspace a single handle would
+ * use.  Simulations may differ in size, parameters and precision.  Every
+ * lbm_batch_step advances all admitted simulations that still have steps
+ * left, in launches of one persistent kernel per kernel variant present
+ * (storage precision, r == 1 or not, equal densities or not); a chunk of
+ * those launches is captured once as a HIP graph and replayed.  The
+ * arithmetic of each simulation is exactly that of lbm_step on its own
+ * (bitwise), whatever the batch holds and whatever the schedule.
+ *
+ * Simulations join with lbm_batch_submit while others run (admitted as
+ * workspace and ids allow) and leave with lbm_batch_retire, so a request
+ * loop can keep the device busy with a changing set of solves.
+ * All calls are made from one host thread; work goes to the stream given
+ * to lbm_batch_create.  Status codes as above; lbm_batch_last_error gives
+ * the message of the last failure.
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+/* How a batch maps tiles to wavefronts.  rows: tile height for every
+ * simulation (0 = each simulation's default).  grid_waves: wavefronts per
+ * launch of each variant's persistent kernel (0 = one wavefront per tile).
+ * chunk: steps per captured graph, 1..1024. */
+typedef struct {
+  int32_t rows;
+  int32_t grid_waves;
+  int32_t chunk;
+  int32_t reserved; /* must be 0 */
+} lbm_schedule;
+
+/* Device bytes one simulation with these parameters takes from a batch
+ * workspace (0 if the parameters are invalid). */
+size_t lbm_batch_instance_bytes(const lbm_params *params);
+
+/* Bytes of batch metadata for up to max_instances simulations; the
+ * workspace must hold this plus the simulations' own bytes. */
+size_t lbm_batch_overhead_bytes(int32_t max_instances);
+
+/* Create a batch over dev_ws (256-byte aligned, ws_bytes long, owned by the
+ * caller and kept alive until lbm_batch_destroy) for at most max_instances
+ * simultaneous simulations (1..65536).  Default schedule: rows 0,
+ * grid_waves 0, chunk 32.  EINVAL: bad arguments; ENOMEM: the workspace
+ * cannot hold the metadata; EDEVICE: HIP failure. */
+lbm_status lbm_batch_create(int32_t max_instances, void *dev_ws, size_t ws_bytes,
+                            void *hip_stream, lbm_batch **out);
+
+/* Admit one simulation: validate params as lbm_create does, take
+ * lbm_batch_instance_bytes(params) from the workspace, set the initial
+ * state from host float64 fields as lbm_init_fields does (synchronising),
+ * and give it nsteps steps to run.  *id receives its id (>= 0).  ENOMEM:
+ * no free id or not enough contiguous free workspace now (nothing is
+ * changed; retry after a retire).  EINVAL: bad parameters or fields. */
+lbm_status lbm_batch_submit(lbm_batch *b, const lbm_params *params, const double *phi,
+                            const double *psi, const double *ux, const double *uy,
+                            int64_t nsteps, int32_t *id);
+
+/* Advance every admitted simulation by min(nsteps, its remaining steps);
+ * asynchronous.  EINVAL: nsteps < 0.  A simulation whose state went
+ * non-finite keeps stepping until a synchronising call on it reports it. */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Steps simulation id still has to run (0 = finished).  No device work. */
+lbm_status lbm_batch_remaining(const lbm_batch *b, int32_t id, int64_t *remaining);
+
+/* As lbm_read_fields / lbm_moments for simulation id (synchronising). */
+lbm_status lbm_batch_read_fields(lbm_batch *b, int32_t id, double *phi, double *psi,
+                                 double *ux, double *uy, double *P);
+lbm_status lbm_batch_moments(lbm_batch *b, int32_t id, lbm_moments_t *out);
+
+/* Remove simulation id and return its workspace (synchronising). */
+lbm_status lbm_batch_retire(lbm_batch *b, int32_t id);
+
+/* Largest workspace block a simulation could be admitted into now. */
+size_t lbm_batch_free_bytes(const lbm_batch *b);
+
+/* Replace the schedule (EINVAL if out of range).  Results do not change. */
+lbm_status lbm_batch_set_schedule(lbm_batch *b, const lbm_schedule *s);
+lbm_status lbm_batch_get_schedule(const lbm_batch *b, lbm_schedule *s);
+
+/* Autotuner: time probe_steps steps of the current batch under each
+ * candidate schedule (tile heights 4, 8, 16 and each simulation's default;
+ * one wavefront per tile or 4, 8, 16 persistent wavefronts per compute
+ * unit) and keep the fastest per site update; *chosen (may be NULL)
+ * receives it.  The probe steps are real steps of the simulations (their
+ * remaining counts go down); results are the same under every schedule.
+ * Synchronising. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int64_t probe_steps, lbm_schedule *chosen);
+
+/* Synchronise and free the batch (the workspace stays the caller's). */
+void lbm_batch_destroy(lbm_batch *b);
+const char *lbm_batch_last_error(const lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm.hip")]
-HEADERS = [os.path.join(CSRC, "lbm_device.h"), os.path.join(ROOT, "include", "lbm.h")]
+HEADERS = [os.path.join(CSRC, "lbm_device.h"), os.path.join(CSRC, "arena.h"),
+           os.path.join(ROOT, "include", "lbm.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

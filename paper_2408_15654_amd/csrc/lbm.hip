@@ -32,15 +32,19 @@
 // the current row only, and every population is written once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lbm.h"
 #include "lbm_device.h"
+#include "arena.h"
 
 using namespace lbm;
 
@@ -683,20 +687,14 @@ __device__ __forceinline__ double lane_pick(bool own, double v) {
 // w+2, whose rebuild needs the old rest values one column further out).
 // The row loop is software-pipelined: the loads for row y+1 are issued
 // before the arithmetic and stores of row y.
+// One tile (strip x rows) of one simulation, executed by one wavefront.
 template <class P, bool GENR, bool HAS_S>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
-lbm_step_kernel(const StepArgs<P> a) {
+__device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
+                                          const int chunk) {
   using R = typename P::R;
   using S = typename P::S;
   using A = typename P::A;
   const int lane = threadIdx.x & (kWave - 1);
-  // the wavefront index is the same on every lane: make it a scalar so all
-  // row arithmetic and row offsets stay in SGPRs
-  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-  const int tile = blockIdx.x * kWavesPerBlock + wave;
-  if (tile >= a.ntiles) return;  // whole wavefronts only
-  const int strip = tile % a.nstrips;
-  const int chunk = tile / a.nstrips;
   const int nx = a.nx, ny = a.ny, walls = a.walls;
   const int x0 = strip * kCols;
   const int w = min(kCols, nx - x0);
@@ -963,6 +961,67 @@ lbm_step_kernel(const StepArgs<P> a) {
   for (int y = y0; y < y1 - 1; ++y) row_step(y, BoolC<true>{});
   row_step(y1 - 1, BoolC<false>{});  // the last row prefetches nothing
   if (bad) *a.flag = 1;
+}
+
+// One time step of one simulation: one wavefront per tile, strip-major
+// (consecutive wavefronts take adjacent strips of the same rows, so each
+// row streams contiguously from memory).
+template <class P, bool GENR, bool HAS_S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
+lbm_step_kernel(const StepArgs<P> a) {
+  // the wavefront index is the same on every lane: make it a scalar so all
+  // row arithmetic and row offsets stay in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int tile = blockIdx.x * kWavesPerBlock + wave;
+  if (tile >= a.ntiles) return;  // whole wavefronts only
+  step_tile<P, GENR, HAS_S>(a, tile % a.nstrips, tile / a.nstrips);
+}
+
+// ------------------------------------------------------------ batched step
+
+// A tile of the batched step: which simulation, which strip and row chunk.
+struct TileRef {
+  int inst, strip, chunk, pad;
+};
+
+// Per simulation of a batch: the step arguments for both ping-pong
+// parities, the parity at the start of the captured chunk, and how many of
+// the chunk's launches it takes part in.
+template <class P>
+struct BatchInst {
+  StepArgs<P> a[2];
+  int parity, steps, pad[2];
+};
+
+// Constant address space: loads through it with a wavefront-uniform address
+// become scalar loads.  The qualifier exists only in the device pass.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LBM_CONST __attribute__((address_space(4)))
+#else
+#define LBM_CONST
+#endif
+
+// Launch k of a captured chunk for every simulation of one kernel variant.
+// Persistent: gridDim.x * 4 wavefronts walk the tile list with a fixed
+// stride; the tile count and the per-simulation descriptors are read from
+// device memory (scalar loads), so a captured graph stays valid when the
+// batch's membership changes between chunks.  Every wavefront leaves the
+// loop after at most ceil(ntiles / stride) tiles.
+template <class P, bool GENR, bool HAS_S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
+lbm_batch_step_kernel(const BatchInst<P> *insts, const TileRef *tiles, const int *ntiles,
+                      int k) {
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int nt = *(const LBM_CONST int *)(ntiles);
+  const int stride = int(gridDim.x) * kWavesPerBlock;
+  for (int t = int(blockIdx.x) * kWavesPerBlock + wave; t < nt; t += stride) {
+    const TileRef tr = ((const LBM_CONST TileRef *)(tiles))[t];
+    const LBM_CONST BatchInst<P> *bi =
+        (const LBM_CONST BatchInst<P> *)(insts) + tr.inst;
+    if (k >= bi->steps) continue;
+    const StepArgs<P> a = bi->a[(bi->parity + k) & 1];
+    step_tile<P, GENR, HAS_S>(a, tr.strip, tr.chunk);
+  }
 }
 
 // ------------------------------------------------------------ site kernels
@@ -1750,6 +1809,566 @@ lbm_status lbm_set_tile_rows(lbm_handle *h, int32_t rows) {
 const char *lbm_step_kernel_name(const lbm_handle *h) {
   (void)h;
   return "lbm_step_kernel";
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ batch runtime
+
+namespace {
+
+
+// Kernel variants: storage precision x (r != 1) x (rho_A != rho_B).
+constexpr int kClasses = 12;
+int class_of(const lbm_handle *h) {
+  return int(h->p.precision) * 4 + (h->genr ? 2 : 0) + (h->has_s ? 1 : 0);
+}
+
+template <class P>
+StepArgs<P> step_args(const lbm_handle *h, int cur) {
+  lbm_handle *hh = const_cast<lbm_handle *>(h);
+  StepArgs<P> a;
+  a.p = make_phys<typename P::R>(h->p);
+  a.sc = make_scales<P>(h->p);
+  a.src = static_cast<const typename P::S *>(pops(hh, cur));
+  a.src_rest = static_cast<const typename P::A *>(rest(hh, cur));
+  a.dst = static_cast<typename P::S *>(pops(hh, cur ^ 1));
+  a.dst_rest = static_cast<typename P::A *>(rest(hh, cur ^ 1));
+  a.aux = static_cast<typename P::A *>(auxp(hh));
+  a.flag = flagp(hh);
+  a.nx = h->p.nx;
+  a.ny = h->p.ny;
+  a.walls = h->p.walls_y;
+  a.nstrips = (h->p.nx + kCols - 1) / kCols;
+  a.rows = h->rows;
+  a.ntiles = a.nstrips * ((h->p.ny + a.rows - 1) / a.rows);
+  return a;
+}
+
+size_t desc_size(int prec) {
+  switch (prec) {
+    case LBM_FP64: return sizeof(BatchInst<F64>);
+    case LBM_FP32: return sizeof(BatchInst<F32>);
+    default: return sizeof(BatchInst<F16>);
+  }
+}
+
+template <class P>
+void fill_desc(void *dst, const lbm_handle *h, int steps) {
+  BatchInst<P> d;
+  std::memset(&d, 0, sizeof d);
+  d.a[0] = step_args<P>(h, 0);
+  d.a[1] = step_args<P>(h, 1);
+  d.parity = h->cur;
+  d.steps = steps;
+  std::memcpy(dst, &d, sizeof d);
+}
+
+template <class P, bool GENR, bool HAS_S>
+void launch_batch(int blocks, hipStream_t st, const void *desc, const TileRef *tiles,
+                  const int *count, int k) {
+  hipLaunchKernelGGL((lbm_batch_step_kernel<P, GENR, HAS_S>), dim3(blocks),
+                     dim3(kWave * kWavesPerBlock), 0, st,
+                     static_cast<const BatchInst<P> *>(desc), tiles, count, k);
+}
+
+template <class P>
+void launch_batch_prec(int c, int blocks, hipStream_t st, const void *desc,
+                       const TileRef *tiles, const int *count, int k) {
+  switch (c & 3) {
+    case 0: launch_batch<P, false, false>(blocks, st, desc, tiles, count, k); break;
+    case 1: launch_batch<P, false, true>(blocks, st, desc, tiles, count, k); break;
+    case 2: launch_batch<P, true, false>(blocks, st, desc, tiles, count, k); break;
+    default: launch_batch<P, true, true>(blocks, st, desc, tiles, count, k); break;
+  }
+}
+
+void launch_batch_class(int c, int blocks, hipStream_t st, const void *desc,
+                        const TileRef *tiles, const int *count, int k) {
+  switch (c / 4) {
+    case LBM_FP64: launch_batch_prec<F64>(c, blocks, st, desc, tiles, count, k); break;
+    case LBM_FP32: launch_batch_prec<F32>(c, blocks, st, desc, tiles, count, k); break;
+    default: launch_batch_prec<F16>(c, blocks, st, desc, tiles, count, k); break;
+  }
+}
+
+}  // namespace
+
+struct lbm_batch {
+  hipStream_t stream = nullptr;   // the caller's stream: all work goes here
+  hipStream_t capture = nullptr;  // library stream used only to record graphs
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  int max_inst = 0;
+  lbm_host::Arena arena;
+  struct Inst {
+    lbm_handle *h = nullptr;  // nullptr: free id
+    size_t off = 0, bytes = 0;
+    int64_t remaining = 0;
+    int up_steps = -1, up_parity = -1;  // what the device descriptor holds
+  };
+  std::vector<Inst> inst;
+  // device metadata (from the workspace) and pinned host staging
+  size_t meta_off = 0, meta_bytes = 0;
+  char *d_desc[3] = {nullptr, nullptr, nullptr};
+  int *d_count = nullptr;
+  TileRef *d_tiles = nullptr;
+  size_t tiles_off = 0, tiles_cap = 0;
+  char *h_desc[3] = {nullptr, nullptr, nullptr};
+  int *h_count = nullptr;
+  TileRef *h_tiles = nullptr;
+  size_t h_tiles_cap = 0;
+  int class_off[kClasses] = {}, class_n[kClasses] = {};
+  bool tiles_dirty = true;
+  lbm_schedule sched = {0, 0, 32, 0};
+  int cus = 256;
+  std::map<std::string, hipGraphExec_t> graphs;
+  std::string err;
+};
+
+namespace {
+
+lbm_status bfail(const lbm_batch *b, lbm_status s, const std::string &msg) {
+  if (b)
+    const_cast<lbm_batch *>(b)->err = msg;
+  else
+    g_create_error = msg;
+  return s;
+}
+
+lbm_status bhip(lbm_batch *b, hipError_t e, const char *what) {
+  if (e == hipSuccess) return LBM_OK;
+  return bfail(b, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void clear_graphs(lbm_batch *b) {
+  for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+size_t meta_bytes_for(int max_inst) {
+  size_t m = 0;
+  for (int p = 0; p < 3; ++p) m += align_up(desc_size(p) * size_t(max_inst), 256);
+  return m + align_up(sizeof(int) * kClasses, 256);
+}
+
+// Rebuild the tile lists (after a change of membership or schedule):
+// simulations grouped by kernel variant, each strip-major.
+lbm_status rebuild_tiles(lbm_batch *b) {
+  size_t total = 0;
+  for (auto &in : b->inst) {
+    if (!in.h) continue;
+    lbm_handle *h = in.h;
+    h->rows = b->sched.rows > 0 ? b->sched.rows : default_rows(h->p);
+    const size_t strips = (h->p.nx + kCols - 1) / kCols;
+    total += strips * size_t((h->p.ny + h->rows - 1) / h->rows);
+  }
+  hipError_t e = hipStreamSynchronize(b->stream);  // staging and tiles idle
+  if (e != hipSuccess) return bhip(b, e, "synchronising");
+  if (total > b->tiles_cap) {  // grow the device tile list
+    const size_t cap = std::max(total, 2 * b->tiles_cap);
+    if (b->d_tiles) b->arena.release(b->tiles_off, b->tiles_cap * sizeof(TileRef));
+    b->d_tiles = nullptr;
+    b->tiles_cap = 0;
+    size_t off;
+    if (!b->arena.alloc_top(cap * sizeof(TileRef), &off))
+      return bfail(b, LBM_ENOMEM, "workspace too small for the tile list");
+    b->tiles_off = off;
+    b->tiles_cap = cap;
+    b->d_tiles = reinterpret_cast<TileRef *>(b->ws + off);
+    clear_graphs(b);
+  }
+  if (total > b->h_tiles_cap) {
+    const size_t cap = std::max(total, 2 * b->h_tiles_cap);
+    if (b->h_tiles) (void)hipHostFree(b->h_tiles);
+    b->h_tiles = nullptr;
+    b->h_tiles_cap = 0;
+    e = hipHostMalloc(reinterpret_cast<void **>(&b->h_tiles), cap * sizeof(TileRef));
+    if (e != hipSuccess) return bhip(b, e, "allocating pinned staging");
+    b->h_tiles_cap = cap;
+  }
+  size_t n = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    b->class_off[c] = int(n);
+    for (int id = 0; id < b->max_inst; ++id) {
+      const lbm_handle *h = b->inst[id].h;
+      if (!h || class_of(h) != c) continue;
+      const int strips = (h->p.nx + kCols - 1) / kCols;
+      const int chunks = (h->p.ny + h->rows - 1) / h->rows;
+      for (int ch = 0; ch < chunks; ++ch)
+        for (int st = 0; st < strips; ++st) b->h_tiles[n++] = TileRef{id, st, ch, 0};
+    }
+    b->class_n[c] = int(n) - b->class_off[c];
+    b->h_count[c] = b->class_n[c];
+  }
+  if (n) {
+    e = hipMemcpyAsync(b->d_tiles, b->h_tiles, n * sizeof(TileRef), hipMemcpyHostToDevice,
+                       b->stream);
+    if (e != hipSuccess) return bhip(b, e, "uploading tiles");
+  }
+  e = hipMemcpyAsync(b->d_count, b->h_count, sizeof(int) * kClasses, hipMemcpyHostToDevice,
+                     b->stream);
+  if (e != hipSuccess) return bhip(b, e, "uploading tile counts");
+  for (auto &in : b->inst) in.up_steps = -1;  // rows may have changed
+  b->tiles_dirty = false;
+  return LBM_OK;
+}
+
+// Upload the descriptors of simulations whose (parity, steps this chunk)
+// changed.  Synchronises only when something must be written.
+lbm_status update_descs(lbm_batch *b, int K) {
+  bool need = false;
+  for (auto &in : b->inst)
+    if (in.h && (in.up_steps != int(std::min<int64_t>(K, in.remaining)) ||
+                 in.up_parity != in.h->cur))
+      need = true;
+  if (!need) return LBM_OK;
+  hipError_t e = hipStreamSynchronize(b->stream);  // staging idle
+  if (e != hipSuccess) return bhip(b, e, "synchronising");
+  for (int id = 0; id < b->max_inst; ++id) {
+    auto &in = b->inst[id];
+    if (!in.h) continue;
+    const int steps = int(std::min<int64_t>(K, in.remaining));
+    if (in.up_steps == steps && in.up_parity == in.h->cur) continue;
+    const int p = in.h->p.precision;
+    char *hd = b->h_desc[p] + size_t(id) * desc_size(p);
+    switch (p) {
+      case LBM_FP64: fill_desc<F64>(hd, in.h, steps); break;
+      case LBM_FP32: fill_desc<F32>(hd, in.h, steps); break;
+      default: fill_desc<F16>(hd, in.h, steps); break;
+    }
+    e = hipMemcpyAsync(b->d_desc[p] + size_t(id) * desc_size(p), hd, desc_size(p),
+                       hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return bhip(b, e, "uploading descriptors");
+    in.up_steps = steps;
+    in.up_parity = in.h->cur;
+  }
+  return LBM_OK;
+}
+
+int class_blocks(const lbm_batch *b, int c) {
+  const int waves = b->sched.grid_waves > 0 ? b->sched.grid_waves : b->class_n[c];
+  return std::max(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
+// The graph of K launches of every variant present, captured once per
+// (K, variants, grid shape, tile storage).
+lbm_status get_graph(lbm_batch *b, int K, hipGraphExec_t *out) {
+  std::string key = std::to_string(K) + ":" + std::to_string(b->sched.grid_waves) + ":" +
+                    std::to_string(reinterpret_cast<uintptr_t>(b->d_tiles));
+  for (int c = 0; c < kClasses; ++c) {
+    key += ":";
+    if (b->class_n[c]) key += std::to_string(b->class_off[c]) + "/" +
+                              std::to_string(class_blocks(b, c));
+  }
+  auto it = b->graphs.find(key);
+  if (it != b->graphs.end()) {
+    *out = it->second;
+    return LBM_OK;
+  }
+  if (b->graphs.size() >= 32) clear_graphs(b);
+  hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return bhip(b, e, "beginning graph capture");
+  for (int k = 0; k < K; ++k)
+    for (int c = 0; c < kClasses; ++c) {
+      if (!b->class_n[c]) continue;
+      launch_batch_class(c, class_blocks(b, c), b->capture, b->d_desc[c / 4],
+                         b->d_tiles + b->class_off[c], b->d_count + c, k);
+    }
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipGetLastError();
+  e = hipStreamEndCapture(b->capture, &g);
+  if (e2 != hipSuccess) e = e2;
+  hipGraphExec_t x = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return bhip(b, e, "capturing the batch graph");
+  b->graphs[key] = x;
+  *out = x;
+  return LBM_OK;
+}
+
+bool schedule_ok(const lbm_schedule *s) {
+  return s && s->rows >= 0 && s->rows <= 4096 && s->grid_waves >= 0 &&
+         s->grid_waves <= (1 << 22) && s->chunk >= 1 && s->chunk <= 1024 && s->reserved == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_instance_bytes(const lbm_params *params) {
+  return lbm_workspace_bytes(params);
+}
+
+size_t lbm_batch_overhead_bytes(int32_t max_instances) {
+  if (max_instances < 1 || max_instances > 65536) return 0;
+  return meta_bytes_for(max_instances);
+}
+
+lbm_status lbm_batch_create(int32_t max_instances, void *dev_ws, size_t ws_bytes,
+                            void *hip_stream, lbm_batch **out) {
+  if (!out) return bfail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_instances < 1 || max_instances > 65536)
+    return bfail(nullptr, LBM_EINVAL, "max_instances must be in 1..65536");
+  if (!dev_ws) return bfail(nullptr, LBM_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_ws) % 256)
+    return bfail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+  const size_t meta = meta_bytes_for(max_instances);
+  if (ws_bytes < meta) return bfail(nullptr, LBM_ENOMEM, "workspace smaller than metadata");
+  lbm_batch *b = new (std::nothrow) lbm_batch();
+  if (!b) return bfail(nullptr, LBM_ENOMEM, "out of host memory");
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->ws = static_cast<char *>(dev_ws);
+  b->ws_bytes = ws_bytes;
+  b->max_inst = max_instances;
+  b->inst.resize(max_instances);
+  b->arena.reset(ws_bytes);
+  size_t off = 0;
+  b->arena.alloc(meta, &off);  // first block: offset 0
+  b->meta_off = off;
+  b->meta_bytes = meta;
+  size_t o = off;
+  for (int p = 0; p < 3; ++p) {
+    b->d_desc[p] = b->ws + o;
+    o += align_up(desc_size(p) * size_t(max_instances), 256);
+  }
+  b->d_count = reinterpret_cast<int *>(b->ws + o);
+  hipError_t e = hipSuccess;
+  for (int p = 0; p < 3 && e == hipSuccess; ++p)
+    e = hipHostMalloc(reinterpret_cast<void **>(&b->h_desc[p]),
+                      desc_size(p) * size_t(max_instances));
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void **>(&b->h_count), sizeof(int) * kClasses);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+  int dev = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) {
+    const std::string m = std::string("creating the batch: ") + hipGetErrorString(e);
+    lbm_batch_destroy(b);
+    return bfail(nullptr, LBM_EDEVICE, m);
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_submit(lbm_batch *b, const lbm_params *params, const double *phi,
+                            const double *psi, const double *ux, const double *uy,
+                            int64_t nsteps, int32_t *id) {
+  if (!b) return LBM_EINVAL;
+  if (!id) return bfail(b, LBM_EINVAL, "id is NULL");
+  if (nsteps < 0) return bfail(b, LBM_EINVAL, "nsteps < 0");
+  if (const char *m = validate(params)) return bfail(b, LBM_EINVAL, m);
+  int slot = -1;
+  for (int i = 0; i < b->max_inst; ++i)
+    if (!b->inst[i].h) {
+      slot = i;
+      break;
+    }
+  if (slot < 0) return bfail(b, LBM_ENOMEM, "no free simulation id");
+  const size_t bytes = lbm_workspace_bytes(params);
+  size_t off;
+  if (!b->arena.alloc(bytes, &off))
+    return bfail(b, LBM_ENOMEM, "not enough contiguous free workspace");
+  lbm_handle *h = nullptr;
+  lbm_status st = lbm_create(params, b->ws + off, bytes, b->stream, &h);
+  if (st == LBM_OK) {
+    st = lbm_init_fields(h, phi, psi, ux, uy);
+    if (st != LBM_OK) {
+      bfail(b, st, h->err);
+      lbm_destroy(h);
+      h = nullptr;
+    }
+  } else {
+    bfail(b, st, g_create_error);
+  }
+  if (st != LBM_OK) {
+    b->arena.release(off, bytes);
+    return st;
+  }
+  auto &in = b->inst[slot];
+  in.h = h;
+  in.off = off;
+  in.bytes = bytes;
+  in.remaining = nsteps;
+  in.up_steps = in.up_parity = -1;
+  b->tiles_dirty = true;
+  *id = slot;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps) {
+  if (!b) return LBM_EINVAL;
+  if (nsteps < 0) return bfail(b, LBM_EINVAL, "nsteps < 0");
+  while (nsteps > 0) {
+    int64_t most = 0;
+    for (auto &in : b->inst)
+      if (in.h) most = std::max(most, in.remaining);
+    if (most == 0) break;  // nothing left to run
+    if (b->tiles_dirty) {
+      lbm_status st = rebuild_tiles(b);
+      if (st != LBM_OK) return st;
+    }
+    const int K = int(std::min<int64_t>({nsteps, int64_t(b->sched.chunk), most}));
+    lbm_status st = update_descs(b, K);
+    if (st != LBM_OK) return st;
+    hipGraphExec_t g;
+    st = get_graph(b, K, &g);
+    if (st != LBM_OK) return st;
+    hipError_t e = hipGraphLaunch(g, b->stream);
+    if (e != hipSuccess) return bhip(b, e, "launching the batch graph");
+    for (auto &in : b->inst) {
+      if (!in.h) continue;
+      const int s = int(std::min<int64_t>(K, in.remaining));
+      in.h->cur ^= s & 1;
+      in.h->step += s;
+      in.remaining -= s;
+    }
+    nsteps -= K;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_remaining(const lbm_batch *b, int32_t id, int64_t *remaining) {
+  if (!b) return LBM_EINVAL;
+  if (!remaining || id < 0 || id >= b->max_inst || !b->inst[id].h)
+    return bfail(b, LBM_EINVAL, "unknown simulation id");
+  *remaining = b->inst[id].remaining;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_read_fields(lbm_batch *b, int32_t id, double *phi, double *psi,
+                                 double *ux, double *uy, double *P) {
+  if (!b) return LBM_EINVAL;
+  if (id < 0 || id >= b->max_inst || !b->inst[id].h)
+    return bfail(b, LBM_EINVAL, "unknown simulation id");
+  lbm_handle *h = b->inst[id].h;
+  lbm_status st = lbm_read_fields(h, phi, psi, ux, uy, P);
+  if (st != LBM_OK) bfail(b, st, h->err);
+  return st;
+}
+
+lbm_status lbm_batch_moments(lbm_batch *b, int32_t id, lbm_moments_t *out) {
+  if (!b) return LBM_EINVAL;
+  if (id < 0 || id >= b->max_inst || !b->inst[id].h)
+    return bfail(b, LBM_EINVAL, "unknown simulation id");
+  lbm_handle *h = b->inst[id].h;
+  lbm_status st = lbm_moments(h, out);
+  if (st != LBM_OK) bfail(b, st, h->err);
+  return st;
+}
+
+lbm_status lbm_batch_retire(lbm_batch *b, int32_t id) {
+  if (!b) return LBM_EINVAL;
+  if (id < 0 || id >= b->max_inst || !b->inst[id].h)
+    return bfail(b, LBM_EINVAL, "unknown simulation id");
+  hipError_t e = hipStreamSynchronize(b->stream);  // no launch still uses it
+  if (e != hipSuccess) return bhip(b, e, "synchronising");
+  auto &in = b->inst[id];
+  lbm_destroy(in.h);
+  b->arena.release(in.off, in.bytes);
+  in = lbm_batch::Inst();
+  b->tiles_dirty = true;
+  return LBM_OK;
+}
+
+size_t lbm_batch_free_bytes(const lbm_batch *b) { return b ? b->arena.largest() : 0; }
+
+lbm_status lbm_batch_set_schedule(lbm_batch *b, const lbm_schedule *s) {
+  if (!b) return LBM_EINVAL;
+  if (!schedule_ok(s)) return bfail(b, LBM_EINVAL, "schedule out of range");
+  b->sched = *s;
+  b->tiles_dirty = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_schedule(const lbm_batch *b, lbm_schedule *s) {
+  if (!b) return LBM_EINVAL;
+  if (!s) return bfail(b, LBM_EINVAL, "s is NULL");
+  *s = b->sched;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch *b, int64_t probe_steps, lbm_schedule *chosen) {
+  if (!b) return LBM_EINVAL;
+  if (probe_steps < 1) return bfail(b, LBM_EINVAL, "probe_steps < 1");
+  const lbm_schedule keep = b->sched;
+  std::vector<lbm_schedule> cands;
+  for (int rows : {0, 4, 8, 16})
+    for (int per_cu : {0, 4, 8, 16})
+      cands.push_back(lbm_schedule{rows, per_cu * b->cus, keep.chunk, 0});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return bhip(b, e, "creating events");
+  lbm_schedule best = keep;
+  double best_t = -1.0;
+  lbm_status st = LBM_OK;
+  for (const auto &c : cands) {
+    b->sched = c;
+    b->tiles_dirty = true;
+    double work = 0.0;  // site updates in the timed probe
+    for (auto &in : b->inst)
+      if (in.h)
+        work += double(in.h->p.nx) * in.h->p.ny * double(std::min(probe_steps, in.remaining));
+    if (work == 0.0) break;
+    st = lbm_batch_step(b, std::min<int64_t>(probe_steps, c.chunk));  // builds graphs
+    if (st != LBM_OK) break;
+    work = 0.0;
+    for (auto &in : b->inst)
+      if (in.h)
+        work += double(in.h->p.nx) * in.h->p.ny * double(std::min(probe_steps, in.remaining));
+    if (work == 0.0) break;
+    e = hipEventRecord(e0, b->stream);
+    if (e == hipSuccess) st = lbm_batch_step(b, probe_steps);
+    if (e == hipSuccess && st == LBM_OK) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess && st == LBM_OK) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess && st == LBM_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess || st != LBM_OK) break;
+    const double t = double(ms) / work;
+    if (best_t < 0.0 || t < best_t) {
+      best_t = t;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) {
+    b->sched = keep;
+    b->tiles_dirty = true;
+    return bhip(b, e, "timing the autotuner probes");
+  }
+  if (st != LBM_OK) {
+    b->sched = keep;
+    b->tiles_dirty = true;
+    return st;
+  }
+  b->sched = best;
+  b->tiles_dirty = true;
+  if (chosen) *chosen = best;
+  return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  clear_graphs(b);
+  for (auto &in : b->inst)
+    if (in.h) lbm_destroy(in.h);
+  for (int p = 0; p < 3; ++p)
+    if (b->h_desc[p]) (void)hipHostFree(b->h_desc[p]);
+  if (b->h_count) (void)hipHostFree(b->h_count);
+  if (b->h_tiles) (void)hipHostFree(b->h_tiles);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  delete b;
+}
+
+const char *lbm_batch_last_error(const lbm_batch *b) {
+  return b ? b->err.c_str() : g_create_error.c_str();
 }
 
 }  // extern "C"

@@ -54,6 +54,12 @@ class lbm_moments_t(ctypes.Structure):
                 ("pad", ctypes.c_int32)]
 
 
+class lbm_schedule(ctypes.Structure):
+    """Tile-to-wavefront schedule of a batch (see include/lbm.h)."""
+    _fields_ = [("rows", ctypes.c_int32), ("grid_waves", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 EXPORTS = ("lbm_workspace_bytes", "lbm_create", "lbm_init_fields", "lbm_step",
            "lbm_read_fields", "lbm_moments", "lbm_state_bytes", "lbm_get_state",
            "lbm_set_state", "lbm_destroy", "lbm_last_error", "lbm_set_tile_rows",
@@ -99,6 +105,34 @@ def load(path: str = LIB_PATH):
     lib.lbm_step_kernel_name.restype = ctypes.c_char_p
     for name in ("lbm_create", "lbm_init_fields", "lbm_step", "lbm_read_fields",
                  "lbm_moments", "lbm_get_state", "lbm_set_state", "lbm_set_tile_rows"):
+        getattr(lib, name).restype = ctypes.c_int
+    # batches
+    B, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    S = ctypes.POINTER(lbm_schedule)
+    lib.lbm_batch_instance_bytes.argtypes = [P]
+    lib.lbm_batch_instance_bytes.restype = ctypes.c_size_t
+    lib.lbm_batch_overhead_bytes.argtypes = [i32]
+    lib.lbm_batch_overhead_bytes.restype = ctypes.c_size_t
+    lib.lbm_batch_create.argtypes = [i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(B)]
+    lib.lbm_batch_submit.argtypes = [B, P, dp, dp, dp, dp, i64, ctypes.POINTER(i32)]
+    lib.lbm_batch_step.argtypes = [B, i64]
+    lib.lbm_batch_remaining.argtypes = [B, i32, ctypes.POINTER(i64)]
+    lib.lbm_batch_read_fields.argtypes = [B, i32, dp, dp, dp, dp, dp]
+    lib.lbm_batch_moments.argtypes = [B, i32, ctypes.POINTER(lbm_moments_t)]
+    lib.lbm_batch_retire.argtypes = [B, i32]
+    lib.lbm_batch_free_bytes.argtypes = [B]
+    lib.lbm_batch_free_bytes.restype = ctypes.c_size_t
+    lib.lbm_batch_set_schedule.argtypes = [B, S]
+    lib.lbm_batch_get_schedule.argtypes = [B, S]
+    lib.lbm_batch_autotune.argtypes = [B, i64, S]
+    lib.lbm_batch_destroy.argtypes = [B]
+    lib.lbm_batch_destroy.restype = None
+    lib.lbm_batch_last_error.argtypes = [B]
+    lib.lbm_batch_last_error.restype = ctypes.c_char_p
+    for name in ("lbm_batch_create", "lbm_batch_submit", "lbm_batch_step",
+                 "lbm_batch_remaining", "lbm_batch_read_fields", "lbm_batch_moments",
+                 "lbm_batch_retire", "lbm_batch_set_schedule", "lbm_batch_get_schedule",
+                 "lbm_batch_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -218,6 +252,130 @@ class Simulation:
         if getattr(self, "_handle", None):
             self.lib.lbm_destroy(self._handle)
             self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent simulations advanced together on one GPU.
+
+    The workspace (the HBM budget) is one torch tensor of `budget_bytes`;
+    simulations are admitted into it with submit() while others run and
+    leave with retire().  Every step() advances all of them by up to n
+    steps (each stops at its own step count)."""
+
+    def __init__(self, budget_bytes: int, max_instances: int = 1024, device: str = "cuda:0",
+                 stream=None):
+        import torch
+
+        self.lib = load()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(budget_bytes), dtype=torch.uint8, device=self.device)
+        self._b = ctypes.c_void_p()
+        st = self.lib.lbm_batch_create(int(max_instances),
+                                       ctypes.c_void_p(self.workspace.data_ptr()),
+                                       int(budget_bytes), ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(self._b))
+        if st != LBM_OK:
+            self._b = None
+            raise LbmError(st, self.lib.lbm_batch_last_error(None).decode())
+        self.shapes = {}
+
+    @staticmethod
+    def instance_bytes(params: dict) -> int:
+        lib = load()
+        c = to_c_params(params)
+        return int(lib.lbm_batch_instance_bytes(ctypes.byref(c)))
+
+    @staticmethod
+    def overhead_bytes(max_instances: int) -> int:
+        return int(load().lbm_batch_overhead_bytes(int(max_instances)))
+
+    def _check(self, st: int):
+        if st == LBM_OK:
+            return
+        msg = self.lib.lbm_batch_last_error(self._b).decode()
+        if st == LBM_ENONFINITE:
+            raise NonFiniteError(st, msg)
+        raise LbmError(st, msg)
+
+    def submit(self, params: dict, phi, psi, ux, uy, nsteps: int) -> int:
+        """Admit a simulation; returns its id.  Raises LbmError with status
+        LBM_ENOMEM when it does not fit now."""
+        c = to_c_params(params)
+        n = c.nx * c.ny
+        arrs = []
+        for a in (phi, psi, ux, uy):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            if a.size != n:
+                raise ValueError("field has the wrong size")
+            arrs.append(a)
+        i = ctypes.c_int32()
+        self._check(self.lib.lbm_batch_submit(self._b, ctypes.byref(c), *[_dptr(a) for a in arrs],
+                                              int(nsteps), ctypes.byref(i)))
+        self.shapes[i.value] = (c.ny, c.nx)
+        return i.value
+
+    def try_submit(self, params: dict, phi, psi, ux, uy, nsteps: int):
+        """submit(), or None when the batch has no room for it now."""
+        try:
+            return self.submit(params, phi, psi, ux, uy, nsteps)
+        except LbmError as e:
+            if e.status == LBM_ENOMEM:
+                return None
+            raise
+
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm_batch_step(self._b, int(n)))
+
+    def remaining(self, i: int) -> int:
+        r = ctypes.c_int64()
+        self._check(self.lib.lbm_batch_remaining(self._b, int(i), ctypes.byref(r)))
+        return r.value
+
+    def read_fields(self, i: int) -> dict:
+        ny, nx = self.shapes[i]
+        out = {k: np.empty((ny, nx)) for k in ("phi", "psi", "ux", "uy", "P")}
+        self._check(self.lib.lbm_batch_read_fields(self._b, int(i), *[_dptr(out[k]) for k in
+                                                                     ("phi", "psi", "ux", "uy", "P")]))
+        return out
+
+    def moments(self, i: int) -> dict:
+        m = lbm_moments_t()
+        self._check(self.lib.lbm_batch_moments(self._b, int(i), ctypes.byref(m)))
+        return {k: getattr(m, k) for k, _ in lbm_moments_t._fields_ if k != "pad"}
+
+    def retire(self, i: int):
+        self._check(self.lib.lbm_batch_retire(self._b, int(i)))
+        self.shapes.pop(i, None)
+
+    def free_bytes(self) -> int:
+        return int(self.lib.lbm_batch_free_bytes(self._b))
+
+    def set_schedule(self, rows=0, grid_waves=0, chunk=32):
+        s = lbm_schedule(int(rows), int(grid_waves), int(chunk), 0)
+        self._check(self.lib.lbm_batch_set_schedule(self._b, ctypes.byref(s)))
+
+    def schedule(self) -> dict:
+        s = lbm_schedule()
+        self._check(self.lib.lbm_batch_get_schedule(self._b, ctypes.byref(s)))
+        return {"rows": s.rows, "grid_waves": s.grid_waves, "chunk": s.chunk}
+
+    def autotune(self, probe_steps: int) -> dict:
+        s = lbm_schedule()
+        self._check(self.lib.lbm_batch_autotune(self._b, int(probe_steps), ctypes.byref(s)))
+        return {"rows": s.rows, "grid_waves": s.grid_waves, "chunk": s.chunk}
+
+    def close(self):
+        if getattr(self, "_b", None):
+            self.lib.lbm_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

@@ -78,3 +78,29 @@ def test_binding_fails_loudly_without_library(tmp_path):
             lbm.load(str(tmp_path / "missing.so"))
         finally:
             lbm._lib = lbm._lib_backup
+
+
+def test_batch_entry_points_validate_without_device():
+    lib = lbm.load()
+    pr = workloads.c1_stationary_drop()
+    c = lbm.to_c_params(pr.params)
+    assert lib.lbm_batch_instance_bytes(ctypes.byref(c)) == lib.lbm_workspace_bytes(ctypes.byref(c))
+    bad = lbm.to_c_params(dict(pr.params, W=0.0))
+    assert lib.lbm_batch_instance_bytes(ctypes.byref(bad)) == 0
+    assert lib.lbm_batch_overhead_bytes(0) == 0
+    assert lib.lbm_batch_overhead_bytes(65537) == 0
+    o1, o2 = lib.lbm_batch_overhead_bytes(1), lib.lbm_batch_overhead_bytes(1000)
+    assert 0 < o1 < o2 and o2 % 256 == 0
+    b = ctypes.c_void_p()
+    for args in ((0, 256, 1 << 30), (8, 8, 1 << 30), (8, None, 1 << 30)):
+        st = lib.lbm_batch_create(args[0], ctypes.c_void_p(args[1]) if args[1] else None,
+                                  args[2], None, ctypes.byref(b))
+        assert st == lbm.LBM_EINVAL, args
+        assert b.value is None
+        assert lib.lbm_batch_last_error(None)
+    st = lib.lbm_batch_create(1000, ctypes.c_void_p(256), o2 - 256, None, ctypes.byref(b))
+    assert st == lbm.LBM_ENOMEM
+    # every call rejects a NULL batch
+    assert lib.lbm_batch_step(None, 1) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_retire(None, 0) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_free_bytes(None) == 0
