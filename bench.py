@@ -121,6 +121,131 @@ def copy_calibration(device="cuda:0", nbytes=1 << 30):
             "GBs": 2 * nbytes / ms / 1e6}
 
 
+def batched_sweep(n=256, steps=400, seq_steps=20, precision="fp32", probe=8):
+    """The batched sweep: n independent drop-in-shear problems (site counts
+    log-uniform in [64^2, 512^2], aspect 2:1), advanced together by the
+    batch runtime, against the same problems solved one at a time with the
+    single-simulation entry points."""
+    import torch
+
+    from paper_2408_15654_amd import lbm, workloads
+
+    probs = workloads.c4_batch(n=n, precision=precision, steps=steps)
+    total_sites = sum(p.sites for p in probs)
+    # one solve at a time: each problem alone, its launches back to back
+    t_seq = 0.0
+    for pr in probs:
+        sim = lbm.Simulation(pr.params)
+        sim.init_fields(*pr.fields0)
+        sim.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(seq_steps)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        sim.close()
+    seq = total_sites * seq_steps / t_seq / 1e6
+
+    budget = (lbm.Batch.overhead_bytes(n) + sum(lbm.Batch.instance_bytes(p.params) for p in probs)
+              + (8 << 20))
+    b = lbm.Batch(budget, max_instances=n)
+    ids = [b.submit(p.params, *p.fields0, 1 << 40) for p in probs]
+
+    def timed(k):
+        b.step(64)  # warm-up (captures the graphs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(k)
+        torch.cuda.synchronize()
+        return total_sites * k / (time.perf_counter() - t0) / 1e6
+
+    b.set_schedule(rows=0, grid_waves=0, chunk=32)
+    untuned = timed(steps)
+    chosen = b.autotune(probe)
+    tuned = timed(steps)
+    hbm = budget
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return {"instances": n, "sites": total_sites, "precision": precision,
+            "one_at_a_time_MLUPS": round(seq, 1), "batched_untuned_MLUPS": round(untuned, 1),
+            "batched_tuned_MLUPS": round(tuned, 1), "tuned_schedule": chosen,
+            "speedup_vs_one_at_a_time": round(tuned / seq, 2),
+            "workspace_bytes": hbm, "timed_steps": steps, "one_at_a_time_steps": seq_steps}
+
+
+def rel_errors(got, want):
+    import numpy as np
+
+    out = {}
+    for k in ("phi", "psi"):
+        out[k] = float(np.abs(got[k] - want[k]).max() / np.abs(want[k]).max())
+    du = np.hypot(got["ux"] - want["ux"], got["uy"] - want["uy"]).max()
+    out["u"] = float(du / max(np.hypot(want["ux"], want["uy"]).max(), 1e-300))
+    return out
+
+
+def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), load=0.7,
+                  max_steps=20000):
+    """The serving stream: Poisson arrivals of drop-in-shear and Marangoni
+    migration solves (sites log-uniform in [128^2, 1024^2], steps uniform in
+    [1000, max_steps]) at `load` times the batch's measured capacity,
+    admitted by HBM budget.  For every 10th request the same problem is
+    re-run alone in float64 on the GPU and the served result's error
+    against it is reported."""
+    import numpy as np
+    import torch
+
+    from paper_2408_15654_amd import lbm, serve
+
+    out = []
+    for prec in precisions:
+        # capacity: the batched rate on the stream's own problem mix
+        reqs, _ = serve.serving_stream(n=n, rate=1.0, precision=prec, max_steps=max_steps)
+        probe = reqs[:48]
+        budget = (lbm.Batch.overhead_bytes(64) + sum(lbm.Batch.instance_bytes(r.params)
+                                                     for r in probe) + (16 << 20))
+        b = lbm.Batch(budget, max_instances=64)
+        for r in probe:
+            b.submit(r.params, *r.fields0, 1 << 40)
+        b.step(64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(512)
+        torch.cuda.synchronize()
+        cap = sum(int(r.params["nx"]) * int(r.params["ny"]) for r in probe) * 512 / (
+            time.perf_counter() - t0) / 1e6
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+        reqs, rate = serve.serving_stream(n=n, precision=prec, max_steps=max_steps,
+                                          offered_MLUPS=load * cap)
+        check = {r.rid for r in reqs if r.rid % 10 == 0}
+        for gb in budgets_gb if prec == "fp32" else budgets_gb[-1:]:
+            srv = serve.Server(int(gb) << 30, max_instances=512, chunk=64)
+            results, stats = srv.run(reqs, keep_fields=check)
+            srv.close()
+            del srv
+            torch.cuda.empty_cache()
+            errs = []
+            by_id = {r.rid: r for r in reqs}
+            for res in results:
+                if res.fields is None:
+                    continue
+                req = by_id[res.rid]
+                sim = lbm.Simulation(dict(req.params, precision="fp64"))
+                sim.init_fields(*req.fields0)
+                sim.step(req.steps)
+                errs.append(rel_errors(res.fields, sim.read_fields()))
+                sim.close()
+            worst = {k: max(e[k] for e in errs) for k in ("phi", "psi", "u")} if errs else {}
+            out.append(dict(stats, precision=prec, budget_GB=gb, capacity_MLUPS=round(cap, 1),
+                            offered_rate_per_s=round(rate, 3), fp64_rerun_checked=len(errs),
+                            worst_rel_err_vs_fp64=worst))
+            print(json.dumps({"serving_run": out[-1]}), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +255,12 @@ def main():
     ap.add_argument("--rows", type=int, default=0, help="tile height override")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="the 256-problem batched sweep instead of the 2048^2 field")
+    ap.add_argument("--serve", action="store_true",
+                    help="the serving stream (p50/p99 latency) instead of the 2048^2 field")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-max-steps", type=int, default=20000)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -143,6 +274,27 @@ def main():
 
     if args.copy_calibration:
         print(json.dumps({"copy_calibration": copy_calibration()}), flush=True)
+        return
+    if args.serve:
+        runs = serving_bench(n=args.serve_requests, max_steps=args.serve_max_steps)
+        main_run = [r for r in runs if r["precision"] == "fp32"][-1]
+        print(json.dumps({
+            "metric": "p50/p99 batched-solve latency and aggregate MLUPS of the serving stream",
+            "value": main_run["aggregate_MLUPS"], "unit": "MLUPS", "n_gpus": 1,
+            "higher_is_better": True, "data": "synthetic", "dtype": "fp32",
+            "latency_p50_s": main_run["latency_p50_s"],
+            "latency_p99_s": main_run["latency_p99_s"],
+            "config": {"workload": f"serving_stream_{args.serve_requests}"},
+            "serving": runs}), flush=True)
+        return
+    if args.batched:
+        r = batched_sweep(steps=args.steps)
+        print(json.dumps({
+            "metric": "aggregate MLUPS of the batched sweep (256 problems)",
+            "value": r["batched_tuned_MLUPS"], "unit": "MLUPS", "n_gpus": 1,
+            "steps": r["timed_steps"], "higher_is_better": True, "data": "synthetic",
+            "dtype": r["precision"], "config": {"workload": "batched_shear_sweep_256"},
+            "batched": r}), flush=True)
         return
 
     pr = workloads.c3_many_drops(precision=args.precision)

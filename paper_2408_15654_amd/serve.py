@@ -1,0 +1,154 @@
+"""Continuous-batching request loop over the batch runtime.
+
+Requests (a problem: parameters, initial fields and a step count) arrive
+over time.  The loop admits every waiting request that fits the batch's
+workspace (its HBM budget) and a free id, advances everything on the device
+in short chunks, and retires finished solves as soon as their steps are done,
+so requests that arrive while others run join the batch at the next chunk.
+All device work is the library's (lbm_batch_*); this module only decides
+when to call it and keeps the clock.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+from . import lbm
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    params: dict
+    fields0: tuple
+    steps: int
+    arrival: float  # seconds after the start of the run
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    sites: int
+    fields: dict | None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    """Serve a stream of requests on one GPU with one batch.
+
+    budget_bytes  device workspace of the batch (its HBM budget)
+    chunk         steps per device round between admissions and retirements
+    keep_fields   read back the final fields of these request ids (others
+                  are retired without a read-back of the fields)
+    """
+
+    def __init__(self, budget_bytes: int, max_instances: int = 512, chunk: int = 64,
+                 schedule: dict | None = None):
+        self.batch = lbm.Batch(budget_bytes, max_instances=max_instances)
+        sched = dict(rows=0, grid_waves=0, chunk=min(chunk, 64))
+        if schedule:
+            sched.update(schedule)
+        self.batch.set_schedule(**sched)
+        self.chunk = chunk
+
+    def run(self, requests: list[Request], keep_fields=frozenset(), clock=time.perf_counter,
+            on_admit=None) -> tuple[list[Result], dict]:
+        import torch
+
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        waiting: collections.deque[Request] = collections.deque()
+        running: dict[int, tuple[Request, float]] = {}
+        results: list[Result] = []
+        site_updates = 0
+        peak_running = 0
+        t0 = clock()
+        while pending or waiting or running:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admit in arrival order while they fit (a request that does not
+            # fit waits; later, smaller ones may still be admitted)
+            for req in list(waiting):
+                sid = self.batch.try_submit(req.params, *req.fields0, req.steps)
+                if sid is None:
+                    continue
+                waiting.remove(req)
+                running[sid] = (req, clock() - t0)
+                if on_admit:
+                    on_admit(req, sid)
+            peak_running = max(peak_running, len(running))
+            if not running:
+                if pending:  # idle until the next arrival
+                    delay = pending[0].arrival - (clock() - t0)
+                    if delay > 0:
+                        time.sleep(min(delay, 0.01))
+                    continue
+                if waiting:
+                    raise RuntimeError("a request does not fit the empty batch")
+                break
+            self.batch.step(self.chunk)
+            torch.cuda.current_stream().synchronize()
+            for sid, (req, adm) in list(running.items()):
+                if self.batch.remaining(sid) > 0:
+                    continue
+                fields = self.batch.read_fields(sid) if req.rid in keep_fields else None
+                self.batch.retire(sid)
+                del running[sid]
+                sites = int(req.params["nx"]) * int(req.params["ny"])
+                site_updates += sites * req.steps
+                results.append(Result(req.rid, req.arrival, adm, clock() - t0, req.steps, sites,
+                                      fields))
+        wall = clock() - t0
+        lat = np.array([r.latency for r in results]) if results else np.zeros(1)
+        stats = {"requests": len(results), "wall_s": round(wall, 3),
+                 "aggregate_MLUPS": round(site_updates / wall / 1e6, 1),
+                 "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+                 "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+                 "latency_max_s": round(float(lat.max()), 4),
+                 "peak_running": peak_running}
+        return results, stats
+
+    def close(self):
+        self.batch.close()
+
+
+def serving_stream(n=200, rate=None, seed=None, precision="fp32", min_side=128, max_side=1024,
+                   min_steps=1000, max_steps=20000, offered_MLUPS=None):
+    """Poisson stream of solves: half drop-in-shear (2:1 channel), half
+    Marangoni migration (square periodic), sites log-uniform in
+    [min_side^2, max_side^2], steps uniform in [min_steps, max_steps],
+    Ca ~ U[0.05, 0.4], beta ~ U[0, 0.8].  The arrival rate is `rate` per
+    second, or the rate at which the stream offers `offered_MLUPS`."""
+    import math
+
+    from . import workloads as W
+
+    rng = np.random.default_rng(W.SEED_BASE + 5 if seed is None else seed)
+    probs = []
+    for i in range(n):
+        N = math.exp(rng.uniform(math.log(min_side ** 2), math.log(max_side ** 2)))
+        steps = int(rng.integers(min_steps, max_steps + 1))
+        if i % 2 == 0:
+            H = max(16, int(round(math.sqrt(N / 2))))
+            pr = W.shear_instance(rng, H, precision=precision, steps=steps)
+        else:
+            pr = W.migration_instance(rng, N, precision=precision, steps=steps)
+        probs.append(pr)
+    work = sum(p.sites * p.steps for p in probs) / 1e6  # million site updates
+    if rate is None:
+        rate = n / (work / offered_MLUPS) if offered_MLUPS else 10.0
+    gaps = rng.exponential(1.0 / rate, size=n)
+    t = np.cumsum(gaps) - gaps[0]
+    reqs = [Request(i, dict(p.params, precision=precision), p.fields0, p.steps, float(t[i]))
+            for i, p in enumerate(probs)]
+    return reqs, rate

@@ -224,13 +224,11 @@ def c3_many_drops(precision="fp32", steps=5000, nx=2048, ny=2048, ndrops=400,
     return Problem(f"c3_drops{nx}x{ny}", p, phi, psi, ux, uy, steps)
 
 
-def c4_instance(rng, precision="fp32", steps=10000) -> Problem:
-    """One drop-in-shear instance of the batched sweep: site count log-uniform
-    in [64^2, 512^2], aspect 2:1, R = H/4, Re = 0.1, nu = min(1.6, 0.0125 H),
-    U = 8 Re nu / H, Ca ~ U[0.05,0.4], beta ~ U[0,0.8], r in {0,1},
-    D=0.005, M=0.02."""
-    N = math.exp(rng.uniform(math.log(64 ** 2), math.log(512 ** 2)))
-    H = max(16, int(round(math.sqrt(N / 2))))
+def shear_instance(rng, H, precision="fp32", steps=10000) -> Problem:
+    """Drop in simple shear in a 2H x H channel with walls at -U/+U: R = H/4,
+    Re = 0.1, nu = min(1.6, 0.0125 H), U = 8 Re nu / H, Ca ~ U[0.05,0.4]
+    (sigma0 = nu U / (2 Ca)), beta ~ U[0,0.8], r in {0,1}, D=0.005, M=0.02."""
+    H = int(H)
     L = 2 * H
     nu = min(1.6, 0.0125 * H)
     Re = 0.1
@@ -248,7 +246,16 @@ def c4_instance(rng, precision="fp32", steps=10000) -> Problem:
     psi = unit_peak(phi)
     x, y = _grid(L, H)
     ux = U * (2.0 * (y + 0.5) / H - 1.0)
-    return Problem(f"c4_shear{L}x{H}", p, phi, psi, ux, np.zeros_like(ux), steps)
+    return Problem(f"shear{L}x{H}", p, phi, psi, ux, np.zeros_like(ux), steps)
+
+
+def c4_instance(rng, precision="fp32", steps=10000) -> Problem:
+    """One drop-in-shear instance of the batched sweep: site count log-uniform
+    in [64^2, 512^2], aspect 2:1 (H = round(sqrt(N/2)), at least 16), then
+    shear_instance."""
+    N = math.exp(rng.uniform(math.log(64 ** 2), math.log(512 ** 2)))
+    H = max(16, int(round(math.sqrt(N / 2))))
+    return shear_instance(rng, H, precision=precision, steps=steps)
 
 
 def c4_batch(n=256, seed=None, precision="fp32", steps=10000):
