@@ -154,6 +154,10 @@ __device__ __forceinline__ void stb(typename P::S *p, unsigned byte_off, typenam
 // buffer descriptors.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 using rsrc_t = __amdgpu_buffer_rsrc_t;
+// Cache policy of the step kernel's stores: non-temporal.  What a step
+// writes is read again only by the next step, long after it has left the
+// caches; measured 1.6% faster than the default policy on the 2048x2048 field.
+constexpr int kStoreNT = 2;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes),
@@ -168,7 +172,7 @@ struct BufIO<float> {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
   }
   static __device__ __forceinline__ void store(float x, rsrc_t r, unsigned v, unsigned s) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, kStoreNT);
   }
 };
 template <>
@@ -182,7 +186,7 @@ struct BufIO<double> {
     u32x2 w;
     w[0] = unsigned(__double2loint(x));
     w[1] = unsigned(__double2hiint(x));
-    __builtin_amdgcn_raw_buffer_store_b64(w, r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, v, s, kStoreNT);
   }
 };
 template <>
@@ -191,7 +195,7 @@ struct BufIO<_Float16> {
     return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
   }
   static __device__ __forceinline__ void store(_Float16 x, rsrc_t r, unsigned v, unsigned s) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, kStoreNT);
   }
 };
 
@@ -501,7 +505,7 @@ struct PairIO<float> {
     u32x2 w;
     w[0] = __float_as_uint(a);
     w[1] = __float_as_uint(b);
-    __builtin_amdgcn_raw_buffer_store_b64(w, r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, v, s, kStoreNT);
   }
 };
 template <>
@@ -520,7 +524,7 @@ struct PairIO<double> {
     w[1] = unsigned(__double2hiint(a));
     w[2] = unsigned(__double2loint(b));
     w[3] = unsigned(__double2hiint(b));
-    __builtin_amdgcn_raw_buffer_store_b128(w, r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, v, s, kStoreNT);
   }
 };
 template <>
@@ -537,7 +541,7 @@ struct PairIO<_Float16> {
     const unsigned short lo = __builtin_bit_cast(unsigned short, a),
                          hi = __builtin_bit_cast(unsigned short, b);
     const unsigned w = unsigned(lo) | (unsigned(hi) << 16);
-    __builtin_amdgcn_raw_buffer_store_b32(w, r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(w, r, v, s, kStoreNT);
   }
 };
 
@@ -558,7 +562,7 @@ struct TripleIO {
     w[0] = __float_as_uint(a);
     w[1] = __float_as_uint(b);
     w[2] = __float_as_uint(c);
-    __builtin_amdgcn_raw_buffer_store_b96(w, r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b96(w, r, v, s, kStoreNT);
   }
 };
 
@@ -1505,11 +1509,11 @@ int default_rows(const lbm_params &p) {
   const long long strips = (p.nx + kCols - 1) / kCols;
   // Many short tiles keep the wavefronts' start-up and drain phases
   // staggered; the two extra halo rows per tile are served mostly from
-  // cache.  Measured on 2048x2048: 4 rows for float32/float16 storage,
-  // about 12 for float64 (fewer resident waves, longer rows).
-  const long long target = p.precision == LBM_FP64 ? 6144 : 16384;
+  // cache.  Measured on 2048x2048: 3 rows for float32, 4 for float16 and
+  // float64 storage.
+  const long long target = p.precision == LBM_FP32 ? 24576 : 16384;
   long long rows = strips * p.ny / target;
-  if (rows < 4) rows = 4;
+  if (rows < 3) rows = 3;
   if (rows > 64) rows = 64;
   return int(rows);
 }
