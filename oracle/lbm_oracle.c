@@ -53,6 +53,9 @@
  *     initial fields (P = 0); the stored previous level is the initial fields,
  *     so the first time differences are taken against them.
  *   - Langmuir EOS: sigma uses min(psi, 1 - 1e-9) inside the logarithm.
+ *   - Prescribed velocity (flow = 1, the setting of Sec. 4.2): u is the
+ *     given initial field at every level, P = 0, only f and g evolve; the
+ *     time differences become (phi - phi_prev) u and (psi - psi_prev) u.
  *
  * Parity unpinned: the factor K = 2/3 in front of the time-difference term
  * tr d_t(rho uu - (Su+uS)/2) of the pressure, Eq. (32b).  No test fixes it
@@ -102,6 +105,8 @@ typedef struct {
   int32_t nx, ny;
   int32_t walls_y; /* 0: periodic in y; 1: half-way bounce-back walls */
   int32_t eos;     /* 0: linear Eq. (20); 1: Langmuir Eq. (19) */
+  int32_t flow;    /* 0: flow from the Navier-Stokes LB; 1: prescribed u */
+  int32_t pad;
   double u_wall_bot, u_wall_top; /* tangential wall speeds */
   double phiA, phiB, W, M, D, r;
   double rhoA, rhoB, muA, muB;
@@ -138,6 +143,7 @@ static int check_params(const or_params *p) {
   if (!(p->rhoA > 0) || !(p->rhoB > 0) || !(p->muA > 0) || !(p->muB > 0))
     return -1;
   if (!(p->r >= 0)) return -1;
+  if (p->flow != 0 && p->flow != 1) return -1;
   return 0;
 }
 
@@ -420,6 +426,12 @@ static void front_half(const or_params *p, const double *fs, const double *gs,
         if (i != 0) sum_h += hi;
       }
       double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho;
+      if (p->flow == 1) {
+        /* prescribed velocity (Sec. 4.2): u is the given field, held in the
+         * previous-level record and never replaced; no flow LB */
+        ux = aux[2 * N + k];
+        uy = aux[3 * N + k];
+      }
       /* previous level */
       double php = aux[0 * N + k], psp = aux[1 * N + k];
       double uxp = aux[2 * N + k], uyp = aux[3 * N + k];
@@ -438,6 +450,7 @@ static void front_half(const or_params *p, const double *fs, const double *gs,
       double P = CS2 / (1.0 - w0) *
                  (sum_h + 0.5 * udr - w0 * AU / (2.0 * CS2) +
                   K * 0.5 * (dTxx + dTyy));
+      if (p->flow == 1) P = 0.0;
       fr->ux[k] = ux;
       fr->uy[k] = uy;
       fr->P[k] = P;
@@ -545,13 +558,14 @@ int or_step(const or_params *p, double *f, double *g, double *h, double *aux,
       }
       or_collide(fi, feq, F, Sf, fo);
       or_collide(gi, geq, G, Sg, go);
-      or_collide(hi, heq, H, Sh, ho);
       for (int i = 0; i < Q; i++) {
         f[i * N + k] = fo[i];
         g[i * N + k] = go[i];
-        h[i * N + k] = ho[i];
       }
       aux[0 * N + k] = s->phi; aux[1 * N + k] = s->psi;
+      if (p->flow == 1) continue; /* prescribed u: h and u are not evolved */
+      or_collide(hi, heq, H, Sh, ho);
+      for (int i = 0; i < Q; i++) h[i * N + k] = ho[i];
       aux[2 * N + k] = s->ux; aux[3 * N + k] = s->uy;
       aux[4 * N + k] = s->Sx; aux[5 * N + k] = s->Sy;
     }

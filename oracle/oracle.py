@@ -25,7 +25,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 # mistakes in a modified copy of the oracle source).
 _LIB_OVERRIDE = os.environ.get("LBM_ORACLE_LIB")
 
-PARAM_KEYS = ("nx", "ny", "walls_y", "eos", "u_wall_bot", "u_wall_top", "phiA",
+PARAM_KEYS = ("nx", "ny", "walls_y", "eos", "flow", "u_wall_bot", "u_wall_top", "phiA",
               "phiB", "W", "M", "D", "r", "rhoA", "rhoB", "muA", "muB",
               "sigma0", "beta", "gx", "gy", "s_free")
 
@@ -34,6 +34,7 @@ class _Params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("walls_y", ctypes.c_int32), ("eos", ctypes.c_int32),
+        ("flow", ctypes.c_int32), ("pad", ctypes.c_int32),
         ("u_wall_bot", ctypes.c_double), ("u_wall_top", ctypes.c_double),
         ("phiA", ctypes.c_double), ("phiB", ctypes.c_double),
         ("W", ctypes.c_double), ("M", ctypes.c_double),
@@ -99,6 +100,8 @@ def make_params(p: dict) -> _Params:
     c.walls_y = int(bool(p.get("walls_y", 0)))
     eos = p.get("eos", "linear")
     c.eos = {"linear": 0, "langmuir": 1, 0: 0, 1: 1}[eos]
+    flow = p.get("flow", "ns")
+    c.flow = {"ns": 0, "prescribed": 1, 0: 0, 1: 1}[flow]
     for k in ("u_wall_bot", "u_wall_top", "gx", "gy"):
         setattr(c, k, float(p.get(k, 0.0)))
     c.phiA = float(p.get("phiA", 1.0))

@@ -23,6 +23,8 @@ Parameter dictionary keys (all lattice units, dx = dt = 1):
   gx, gy            body force per unit mass
   s_free            3x3 free relaxation rates (f: s2,s3,s4; g: s2,s3,s4;
                     h: s1,s3,s4), default all 1.0
+  flow              'ns' (velocity from the Navier-Stokes LB, default) or
+                    'prescribed' (u held at the initial field, Sec. 4.2)
   precision         'fp64', 'fp32' or 'fp16dev' (library only)
 """
 from __future__ import annotations
@@ -278,6 +280,22 @@ def migration_instance(rng, N, precision="fp32", steps=1000) -> Problem:
     psi = (1.0 + 0.5 * np.cos(th)) * unit_peak(phi)
     z = np.zeros_like(phi)
     return Problem(f"migration{n}", p, phi, psi, z, z.copy(), steps)
+
+
+def e2_convection(nx=100, R=20.0, u=(0.05, 0.0), steps=2000, r=1.0, precision="fp64",
+                  **kw) -> Problem:
+    """Sec. 4.2 in lattice units: domain [-0.5,0.5]^2 with dx = 0.01,
+    dt = 0.001 -> 100x100 periodic, R = 0.2 -> 20, W = 4, M_phi = 0.1 ->
+    M = M_phi dt/dx^2 = 1.0, D = 0.2 -> 2.0, prescribed uniform u = (0.5, 0)
+    -> 0.05, psi = phi initially; t = 2 -> 2000 steps (one crossing of the
+    periodic domain)."""
+    p = base_params(nx, nx, W=4.0, M=1.0, D=2.0, r=r, sigma0=0.0, beta=0.0,
+                    flow="prescribed", precision=precision)
+    p.update(kw)
+    phi, _ = single_drop(nx, nx, R, W=4.0)
+    ux = np.full_like(phi, u[0])
+    uy = np.full_like(phi, u[1])
+    return Problem("e2_convection", p, phi, phi.copy(), ux, uy, steps)
 
 
 # ------------------------------------------------------- pin problems

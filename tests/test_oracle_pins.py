@@ -514,3 +514,70 @@ def test_galilean_translation_with_density_ratio():
         rms.append(np.sqrt((d ** 2).mean()) / U)
     assert rms[0] < 0.05
     assert 0.15 < rms[1] / rms[0] < 0.4
+
+
+# ------------------------------------------------ prescribed velocity (Sec. 4.2)
+
+def test_prescribed_zero_velocity_equals_flow_at_rest():
+    """With sigma0 = 0, equal densities and u0 = 0 the Navier-Stokes LB stays
+    exactly at rest (no force, P = 0), so its phi/psi step must be the
+    prescribed-velocity step with u = 0: compared bitwise."""
+    pr = W.c1_stationary_drop(sigma0=0.0, beta=0.0)
+    ns = O.OracleSim(pr.params, *pr.fields0)
+    ns.step(150)
+    fn = ns.fields()
+    assert np.abs(fn["ux"]).max() == 0.0 and np.abs(fn["uy"]).max() == 0.0
+    pp = O.OracleSim(dict(pr.params, flow="prescribed"), *pr.fields0)
+    pp.step(150)
+    fp = pp.fields()
+    assert np.array_equal(fn["phi"], fp["phi"]) and np.array_equal(fn["psi"], fp["psi"])
+    assert np.abs(fp["P"]).max() == 0.0
+
+
+def _centroid_x(phi):
+    n = phi.shape[1]
+    w = phi.sum(axis=0)
+    ang = 2 * np.pi * np.arange(n) / n
+    return np.angle((w * np.exp(1j * ang)).sum()) * n / (2 * np.pi)
+
+
+def test_prescribed_uniform_flow_translates_the_drop():
+    """Sec. 4.2 (drop in a uniform prescribed flow): Sum phi and Sum psi are
+    conserved, the drop's centroid moves by u t, and the field equals the
+    zero-velocity run shifted by u t (Galilean invariance of the advected
+    Allen-Cahn and surfactant equations) up to the scheme's O(u) error."""
+    pr = W.e2_convection()                  # u = (0.05, 0), 100 x 100, periodic
+    pz = W.e2_convection(u=(0.0, 0.0))
+    a = O.OracleSim(pr.params, *pr.fields0)
+    a.step(1000)                            # u t = 50 sites
+    fa = a.fields()
+    b = O.OracleSim(pz.params, *pz.fields0)
+    b.step(1000)
+    fb = b.fields()
+    assert abs(fa["phi"].sum() / pr.phi0.sum() - 1) < 1e-12
+    assert abs(fa["psi"].sum() / pr.psi0.sum() - 1) < 1e-12
+    shift = (_centroid_x(fa["phi"]) - _centroid_x(pr.phi0)) % 100
+    assert abs(shift - 50.0) < 0.25, shift
+    assert np.abs(fa["phi"] - np.roll(fb["phi"], 50, axis=1)).max() < 0.05
+    assert (np.abs(fa["psi"] - np.roll(fb["psi"], 50, axis=1)).max()
+            < 0.1 * fb["psi"].max())
+    # the opposite flow moves it the other way
+    pm = W.e2_convection(u=(-0.05, 0.0))
+    m = O.OracleSim(pm.params, *pm.fields0)
+    m.step(200)
+    back = (_centroid_x(m.fields()["phi"]) - _centroid_x(pr.phi0)) % 100
+    assert abs(back - 90.0) < 0.25, back
+
+
+@pytest.mark.parametrize("r,tol", [(1.0, 0.06), (2.0, 0.03)])
+def test_prescribed_surfactant_relaxes_to_interface_profile(r, tol):
+    """Sec. 4.2: psi = phi initially reorganises onto the interface.  For
+    r >= 1 the normal flux drives psi to the equilibrium of Eq. (13), a
+    multiple of delta(phi) ~ 4 phi (1 - phi), with the total conserved."""
+    q = W.e2_convection(u=(0.0, 0.0), r=r)
+    s = O.OracleSim(q.params, *q.fields0)
+    s.step(2000)
+    f = s.fields()
+    unit = 4 * f["phi"] * (1 - f["phi"])
+    c = q.psi0.sum() / unit.sum()
+    assert np.abs(f["psi"] - c * unit).max() < tol * f["psi"].max()
