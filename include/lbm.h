@@ -63,6 +63,14 @@ typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16DEV = 2 } lbm_precision;
 /* Equation of state sigma(psi): linear Eq. (20) or Langmuir Eq. (19). */
 typedef enum { LBM_EOS_LINEAR = 0, LBM_EOS_LANGMUIR = 1 } lbm_eos;
 
+/* Where the velocity comes from.  LBM_FLOW_NS: the Navier-Stokes LB of
+ * Sec. 3.3, coupled to phi and psi.  LBM_FLOW_PRESCRIBED: the velocity is
+ * the field given to lbm_init_fields, held fixed, as in the drop-convection
+ * test of Sec. 4.2; only the phase-field and surfactant LBs evolve (f, g),
+ * the time differences of Eqs. (22), (26) become (phi - phi_prev) u and
+ * (psi - psi_prev) u, and lbm_read_fields returns that u and P = 0. */
+typedef enum { LBM_FLOW_NS = 0, LBM_FLOW_PRESCRIBED = 1 } lbm_flow;
+
 /* Problem parameters, named after the paper's statement of the problem.
  * Relaxation rates follow from the transport coefficients:
  *   1/s1^f = M/c_s^2 + 1/2        (Eq. (23), tau_phi = 3M + 1/2)
@@ -75,7 +83,7 @@ typedef struct {
                            below row 0 and above row ny-1 (Sec. 4)          */
   int32_t eos;          /* lbm_eos                                          */
   int32_t precision;    /* lbm_precision                                    */
-  int32_t reserved;     /* must be 0                                        */
+  int32_t flow;         /* lbm_flow                                         */
   double u_wall_bot;    /* tangential (x) speed of the bottom wall          */
   double u_wall_top;    /* tangential (x) speed of the top wall             */
   double phiA, phiB;    /* order parameter in fluids A and B, phiA > phiB   */

@@ -692,7 +692,9 @@ __device__ __forceinline__ double lane_pick(bool own, double v) {
 // The row loop is software-pipelined: the loads for row y+1 are issued
 // before the arithmetic and stores of row y.
 // One tile (strip x rows) of one simulation, executed by one wavefront.
-template <class P, bool GENR, bool HAS_S>
+// NS: velocity from the Navier-Stokes LB (h); otherwise prescribed (u held
+// in aux slots 0, 1; only f and g evolve).
+template <class P, bool GENR, bool HAS_S, bool NS>
 __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
                                           const int chunk) {
   using R = typename P::R;
@@ -749,16 +751,16 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   };
   // loads of row y that the rebuild of row y+1 does not need
   auto load_row = [&](int y, R *h, R &uxp, R &uyp, R &Sxp, R &Syp) {
-    Pull<P>::h(rsrc, hb, nxh, row_offsets(y, ny, walls, rows_s), co, sc.hi, h);
+    if constexpr (NS) Pull<P>::h(rsrc, hb, nxh, row_offsets(y, ny, walls, rows_s), co, sc.hi, h);
     A u, v;
-    if constexpr (!P::HDEV) {
+    if constexpr (!P::HDEV || !NS) {  // u: previous level, or the prescribed field
       PairIO<A>::load(raux, baux, unsigned(y) * arow, u, v);
       uxp = R(u);
       uyp = R(v);
     } else {  // from the rest record (P, rho u) instead
       uxp = uyp = R(0);
     }
-    if (HAS_S) {
+    if (HAS_S && NS) {
       PairIO<A>::load(raux, baux + P::kAuxS * EA, unsigned(y) * arow, u, v);
       Sxp = R(u);
       Syp = R(v);
@@ -768,7 +770,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   };
   // old (P, rho ux, rho uy) of this column at row y (float16 storage only)
   auto hrest_at = [&](int y, HRest<R> &v) {
-    if constexpr (P::HDEV)
+    if constexpr (P::HDEV && NS)
       TripleIO::load(rrest, brest + 2 * EA, unsigned(wrap_row(y, ny, walls)) * rrow, v.P, v.jx,
                      v.jy);
   };
@@ -824,7 +826,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   load_row(y0, hr, uxr, uyr, Sxr, Syr);
   // rest (P, rho u) of rows y-1, y, y+1 and the prefetched y+2
   HRest<R> Hm{}, Hc{}, Hn{}, Hq{};
-  if constexpr (P::HDEV) {
+  if constexpr (P::HDEV && NS) {
     hrest_at(y0 - 1, Hm);
     hrest_at(y0, Hc);
     hrest_at(y0 + 1, Hn);
@@ -852,7 +854,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     for (int i = 0; i < 8; ++i) h[i] = hr[i];
     R uxp = uxr, uyp = uyr;
     const R Sxp = Sxr, Syp = Syr;
-    if constexpr (P::HDEV) {  // add back the rest parts of the arriving h
+    if constexpr (P::HDEV && NS) {  // add back the rest parts of the arriving h
       R b[8];
       h_arrival_basis(window(Hm.P, Hc.P, Hn.P), window(Hm.jx, Hc.jx, Hn.jx),
                       window(Hm.jy, Hc.jy, Hn.jy), walls && y == 0, walls && y == ny - 1, b);
@@ -879,7 +881,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
 
     const R php = X1, psp = Y1;
     const bool bot = walls && y == 0, top = walls && y == ny - 1;
-    wall_terms(bot, top, rho_of(p, php), p.uwb, p.uwt, h);
+    if constexpr (NS) wall_terms(bot, top, rho_of(p, php), p.uwb, p.uwt, h);
 
     // stencils from the register window
     const Nine<R> vphi = window(phm, phc, phn);
@@ -890,15 +892,21 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     const R lphi = lap9(vphi);
 
     Front<R> s;
-    site_front<R, HAS_S>(p, s, phc, psc, sgc, gfx, gfy, lphi, gsx, gsy, h, php, psp, uxp,
-                         uyp, Sxp, Syp);
+    if constexpr (NS)
+      site_front<R, HAS_S>(p, s, phc, psc, sgc, gfx, gfy, lphi, gsx, gsy, h, php, psp, uxp,
+                           uyp, Sxp, Syp);
+    else
+      site_front_prescribed<R>(p, s, phc, psc, gfx, gfy, uxp, uyp, php, psp);
     if (GENR) {
       const Nine<R> vpsi = window(psm, psc, psn);
       grad9(vpsi, s.gpx, s.gpy);
     } else {
       s.gpx = s.gpy = R(0);
     }
-    collide_site<R, GENR>(p, s, dc, qc, h);
+    if constexpr (NS)
+      collide_site<R, GENR>(p, s, dc, qc, h);
+    else
+      collide_fg<R, GENR>(p, s, dc, qc);
 
     const unsigned rcs = unsigned(y) * rows_s;
     if constexpr (P::SCALED) {
@@ -912,25 +920,27 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
         PairIO<S>::store(S(lane_pick(interior, dc[i])), S(lane_pick(interior, qc[i])), rdst,
                          cs.p0, rcs + unsigned(i) * nxb);
     }
-    if constexpr (P::HDEV) {  // h as deviations from this site's new rest parts
+    if constexpr (P::HDEV && NS) {  // h as deviations from this site's new rest parts
       const HRest<R> hn = {s.P, s.jx, s.jy};
       R b[8];
       h_store_basis(hn, b);
 #pragma unroll
       for (int i = 0; i < 8; ++i) h[i] -= b[i];
     }
+    if constexpr (NS) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      bst<P>(lane_pick(interior, h[i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh, sc.h);
+      for (int i = 0; i < 8; ++i)
+        bst<P>(lane_pick(interior, h[i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh, sc.h);
+    }
     PairIO<A>::store(A(lane_pick(interior, phc)), A(lane_pick(interior, psc)), rdrest,
                      brest_s, unsigned(y) * rrow);
-    if constexpr (P::HDEV)
+    if constexpr (P::HDEV && NS)
       TripleIO::store(lane_pick(interior, s.P), lane_pick(interior, s.jx),
                       lane_pick(interior, s.jy), rdrest, brest_s + 2 * EA, unsigned(y) * rrow);
-    else
+    else if constexpr (NS)
       PairIO<A>::store(A(lane_pick(interior, s.ux)), A(lane_pick(interior, s.uy)), raux,
                        baux_s, unsigned(y) * arow);
-    if (HAS_S)
+    if (HAS_S && NS)
       PairIO<A>::store(A(lane_pick(interior, s.Sx)), A(lane_pick(interior, s.Sy)), raux,
                        baux_s + P::kAuxS * EA, unsigned(y) * arow);
     bad |= interior && !isfinite(phc + psc + s.ux + s.uy);
@@ -955,7 +965,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     Y1 = Y2;
     Y2 = Y3;
     Y3 = Y4;
-    if constexpr (P::HDEV) {
+    if constexpr (P::HDEV && NS) {
       Hm = Hc;
       Hc = Hn;
       Hn = Hq;
@@ -970,7 +980,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
 // One time step of one simulation: one wavefront per tile, strip-major
 // (consecutive wavefronts take adjacent strips of the same rows, so each
 // row streams contiguously from memory).
-template <class P, bool GENR, bool HAS_S>
+template <class P, bool GENR, bool HAS_S, bool NS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
 lbm_step_kernel(const StepArgs<P> a) {
   // the wavefront index is the same on every lane: make it a scalar so all
@@ -978,7 +988,7 @@ lbm_step_kernel(const StepArgs<P> a) {
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int tile = blockIdx.x * kWavesPerBlock + wave;
   if (tile >= a.ntiles) return;  // whole wavefronts only
-  step_tile<P, GENR, HAS_S>(a, tile % a.nstrips, tile / a.nstrips);
+  step_tile<P, GENR, HAS_S, NS>(a, tile % a.nstrips, tile / a.nstrips);
 }
 
 // ------------------------------------------------------------ batched step
@@ -1011,7 +1021,7 @@ struct BatchInst {
 // device memory (scalar loads), so a captured graph stays valid when the
 // batch's membership changes between chunks.  Every wavefront leaves the
 // loop after at most ceil(ntiles / stride) tiles.
-template <class P, bool GENR, bool HAS_S>
+template <class P, bool GENR, bool HAS_S, bool NS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
 lbm_batch_step_kernel(const BatchInst<P> *insts, const TileRef *tiles, const int *ntiles,
                       int k) {
@@ -1024,7 +1034,7 @@ lbm_batch_step_kernel(const BatchInst<P> *insts, const TileRef *tiles, const int
         (const LBM_CONST BatchInst<P> *)(insts) + tr.inst;
     if (k >= bi->steps) continue;
     const StepArgs<P> a = bi->a[(bi->parity + k) & 1];
-    step_tile<P, GENR, HAS_S>(a, tr.strip, tr.chunk);
+    step_tile<P, GENR, HAS_S, NS>(a, tr.strip, tr.chunk);
   }
 }
 
@@ -1077,6 +1087,7 @@ struct SiteArgs {
   Scales<P> sc;
   long long plane;
   int nx, ny, walls;
+  int ns;  // 1: velocity from the Navier-Stokes LB; 0: prescribed (aux slots 0, 1)
 };
 
 // Initial state in float64: post-collision populations := equilibria of
@@ -1137,6 +1148,11 @@ lbm_init_kernel(const SiteArgs<P> a, const Phys<double> p) {
   }
   a.dst_rest[rest_idx<P>(0, y, x, nx)] = A(phi);
   a.dst_rest[rest_idx<P>(1, y, x, nx)] = A(psi);
+  if (!a.ns) {  // prescribed velocity, held in aux slots 0, 1 for good
+    a.aux[aux_idx<P>(0, y, x, nx)] = A(ux);
+    a.aux[aux_idx<P>(1, y, x, nx)] = A(uy);
+    return;
+  }
   if constexpr (P::HDEV) {
     a.dst_rest[rest_idx<P>(2, y, x, nx)] = A(0);
     a.dst_rest[rest_idx<P>(3, y, x, nx)] = A(jx);
@@ -1205,6 +1221,14 @@ lbm_macro_fields_kernel(const SiteArgs<P> a, const Phys<typename P::R> p) {
   const R lphi = lap9(vphi);
   const R php = R(a.src_rest[rest_idx<P>(0, y, x, nx)]);
   const R psp = R(a.src_rest[rest_idx<P>(1, y, x, nx)]);
+  if (!a.ns) {  // prescribed velocity: u as given, P = 0
+    a.scratch[k] = double(vphi.c);
+    a.scratch[pl + k] = double(sc[pl + k]);
+    a.scratch[2 * pl + k] = double(a.aux[aux_idx<P>(0, y, x, nx)]);
+    a.scratch[3 * pl + k] = double(a.aux[aux_idx<P>(1, y, x, nx)]);
+    a.scratch[4 * pl + k] = 0.0;
+    return;
+  }
   const R Sxp = HAS_S ? R(a.aux[aux_idx<P>(P::kAuxS, y, x, nx)]) : R(0);
   const R Syp = HAS_S ? R(a.aux[aux_idx<P>(P::kAuxS + 1, y, x, nx)]) : R(0);
   const RowN r = row_numbers(y, a.ny, a.walls);
@@ -1352,7 +1376,7 @@ const char *validate(const lbm_params *p) {
   if (p->eos != LBM_EOS_LINEAR && p->eos != LBM_EOS_LANGMUIR) return "unknown eos";
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32 && p->precision != LBM_FP16DEV)
     return "unknown precision";
-  if (p->reserved != 0) return "reserved must be 0";
+  if (p->flow != LBM_FLOW_NS && p->flow != LBM_FLOW_PRESCRIBED) return "unknown flow";
   {
     // the step kernel addresses each population copy through one buffer
     // resource with 32-bit byte offsets
@@ -1462,7 +1486,7 @@ struct lbm_handle {
   int64_t step;
   bool valid;
   int rows;
-  bool genr, has_s;
+  bool genr, has_s, ns;
   std::string err;
 };
 
@@ -1502,6 +1526,7 @@ SiteArgs<P> site_args(lbm_handle *h) {
   a.nx = h->p.nx;
   a.ny = h->p.ny;
   a.walls = h->p.walls_y;
+  a.ns = h->ns ? 1 : 0;
   return a;
 }
 
@@ -1518,7 +1543,7 @@ int default_rows(const lbm_params &p) {
   return int(rows);
 }
 
-template <class P, bool GENR, bool HAS_S>
+template <class P, bool GENR, bool HAS_S, bool NS>
 hipError_t launch_step(lbm_handle *h) {
   StepArgs<P> a;
   a.p = make_phys<typename P::R>(h->p);
@@ -1536,16 +1561,18 @@ hipError_t launch_step(lbm_handle *h) {
   a.rows = h->rows;
   a.ntiles = a.nstrips * ((h->p.ny + a.rows - 1) / a.rows);
   const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((lbm_step_kernel<P, GENR, HAS_S>), dim3(blocks),
+  hipLaunchKernelGGL((lbm_step_kernel<P, GENR, HAS_S, NS>), dim3(blocks),
                      dim3(kWave * kWavesPerBlock), 0, h->stream, a);
   return hipGetLastError();
 }
 
 template <class P>
 hipError_t launch_step_prec(lbm_handle *h) {
+  if (!h->ns)
+    return h->genr ? launch_step<P, true, false, false>(h) : launch_step<P, false, false, false>(h);
   if (h->genr)
-    return h->has_s ? launch_step<P, true, true>(h) : launch_step<P, true, false>(h);
-  return h->has_s ? launch_step<P, false, true>(h) : launch_step<P, false, false>(h);
+    return h->has_s ? launch_step<P, true, true, true>(h) : launch_step<P, true, false, true>(h);
+  return h->has_s ? launch_step<P, false, true, true>(h) : launch_step<P, false, false, true>(h);
 }
 
 hipError_t run_step(lbm_handle *h) {
@@ -1643,7 +1670,8 @@ lbm_status lbm_create(const lbm_params *params, void *dev_ws, size_t ws_bytes,
   h->valid = false;
   h->rows = default_rows(*params);
   h->genr = params->r != 1.0;
-  h->has_s = params->rhoA != params->rhoB;
+  h->ns = params->flow == LBM_FLOW_NS;
+  h->has_s = h->ns && params->rhoA != params->rhoB;
   *out = h;
   return LBM_OK;
 }
@@ -1822,10 +1850,11 @@ const char *lbm_step_kernel_name(const lbm_handle *h) {
 namespace {
 
 
-// Kernel variants: storage precision x (r != 1) x (rho_A != rho_B).
-constexpr int kClasses = 12;
+// Kernel variants: storage precision x prescribed velocity x (r != 1) x
+// (rho_A != rho_B).
+constexpr int kClasses = 24;
 int class_of(const lbm_handle *h) {
-  return int(h->p.precision) * 4 + (h->genr ? 2 : 0) + (h->has_s ? 1 : 0);
+  return int(h->p.precision) * 8 + (h->ns ? 0 : 4) + (h->genr ? 2 : 0) + (h->has_s ? 1 : 0);
 }
 
 template <class P>
@@ -1868,10 +1897,10 @@ void fill_desc(void *dst, const lbm_handle *h, int steps) {
   std::memcpy(dst, &d, sizeof d);
 }
 
-template <class P, bool GENR, bool HAS_S>
+template <class P, bool GENR, bool HAS_S, bool NS>
 void launch_batch(int blocks, hipStream_t st, const void *desc, const TileRef *tiles,
                   const int *count, int k) {
-  hipLaunchKernelGGL((lbm_batch_step_kernel<P, GENR, HAS_S>), dim3(blocks),
+  hipLaunchKernelGGL((lbm_batch_step_kernel<P, GENR, HAS_S, NS>), dim3(blocks),
                      dim3(kWave * kWavesPerBlock), 0, st,
                      static_cast<const BatchInst<P> *>(desc), tiles, count, k);
 }
@@ -1879,17 +1908,19 @@ void launch_batch(int blocks, hipStream_t st, const void *desc, const TileRef *t
 template <class P>
 void launch_batch_prec(int c, int blocks, hipStream_t st, const void *desc,
                        const TileRef *tiles, const int *count, int k) {
-  switch (c & 3) {
-    case 0: launch_batch<P, false, false>(blocks, st, desc, tiles, count, k); break;
-    case 1: launch_batch<P, false, true>(blocks, st, desc, tiles, count, k); break;
-    case 2: launch_batch<P, true, false>(blocks, st, desc, tiles, count, k); break;
-    default: launch_batch<P, true, true>(blocks, st, desc, tiles, count, k); break;
+  switch (c & 7) {
+    case 0: launch_batch<P, false, false, true>(blocks, st, desc, tiles, count, k); break;
+    case 1: launch_batch<P, false, true, true>(blocks, st, desc, tiles, count, k); break;
+    case 2: launch_batch<P, true, false, true>(blocks, st, desc, tiles, count, k); break;
+    case 3: launch_batch<P, true, true, true>(blocks, st, desc, tiles, count, k); break;
+    case 4: launch_batch<P, false, false, false>(blocks, st, desc, tiles, count, k); break;
+    default: launch_batch<P, true, false, false>(blocks, st, desc, tiles, count, k); break;
   }
 }
 
 void launch_batch_class(int c, int blocks, hipStream_t st, const void *desc,
                         const TileRef *tiles, const int *count, int k) {
-  switch (c / 4) {
+  switch (c / 8) {
     case LBM_FP64: launch_batch_prec<F64>(c, blocks, st, desc, tiles, count, k); break;
     case LBM_FP32: launch_batch_prec<F32>(c, blocks, st, desc, tiles, count, k); break;
     default: launch_batch_prec<F16>(c, blocks, st, desc, tiles, count, k); break;
@@ -2076,7 +2107,7 @@ lbm_status get_graph(lbm_batch *b, int K, hipGraphExec_t *out) {
   for (int k = 0; k < K; ++k)
     for (int c = 0; c < kClasses; ++c) {
       if (!b->class_n[c]) continue;
-      launch_batch_class(c, class_blocks(b, c), b->capture, b->d_desc[c / 4],
+      launch_batch_class(c, class_blocks(b, c), b->capture, b->d_desc[c / 8],
                          b->d_tiles + b->class_off[c], b->d_count + c, k);
     }
   hipGraph_t g = nullptr;

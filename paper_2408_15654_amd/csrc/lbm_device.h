@@ -281,10 +281,36 @@ __device__ __forceinline__ void collide_flow(R* h, const Front<R>& s, R s3, R s4
   h[7] = R(0.25) * (-m5 + m6 - m7 + m8);
 }
 
-// The three collisions of one site.  f, g: 9 populations; h: h_1..h_8.
+// Front of one site under a prescribed velocity (Sec. 4.2): u is given, so
+// only what the phase-field and surfactant collisions use is formed; the
+// previous level's velocity is the same u.
+template <class R>
+__device__ __forceinline__ void site_front_prescribed(const Phys<R>& p, Front<R>& s, R phi,
+                                                      R psi, R gfx, R gfy, R ux, R uy,
+                                                      R php, R psp) {
+  s.phi = phi;
+  s.psi = psi;
+  const R gn = sqrt(gfx * gfx + gfy * gfy);
+  const R inv = R(1) / (gn + p.eps_n);
+  s.nx = gfx * inv;
+  s.ny = gfy * inv;
+  const R qa = p.phiA - phi, qb = phi - p.phiB, qab = p.phiAB - phi - phi;
+  s.delta = p.c4W * (qa * qb);
+  s.a = p.c4W * qab;
+  s.ux = ux;
+  s.uy = uy;
+  s.dpux = phi * ux - php * ux;
+  s.dpuy = phi * uy - php * uy;
+  s.dqux = psi * ux - psp * ux;
+  s.dquy = psi * uy - psp * uy;
+  s.rho = R(1);
+  s.jx = s.jy = s.Sx = s.Sy = s.Fx = s.Fy = s.grx = s.gry = s.P = R(0);
+  s.dTxx = s.dTxy = s.dTyy = s.s2h = R(0);
+}
+
+// The phase-field and surfactant collisions of one site (9 populations each).
 template <class R, bool GENR>
-__device__ __forceinline__ void collide_site(const Phys<R>& p, const Front<R>& s,
-                                             R* f, R* g, R* h) {
+__device__ __forceinline__ void collide_fg(const Phys<R>& p, const Front<R>& s, R* f, R* g) {
   // phase field: V = 3 d_t(phi u) + delta n  (Eq. (22))
   collide_cde(f, s.phi, s.ux, s.uy, R(3) * s.dpux + s.delta * s.nx,
               R(3) * s.dpuy + s.delta * s.ny, p.s1f, p.s2f, p.s3f, p.s4f);
@@ -303,6 +329,13 @@ __device__ __forceinline__ void collide_site(const Phys<R>& p, const Front<R>& s
   }
   collide_cde(g, s.psi, s.ux, s.uy, R(3) * s.dqux + jx, R(3) * s.dquy + jy,
               p.s1g, p.s2g, p.s3g, p.s4g);
+}
+
+// The three collisions of one site.  f, g: 9 populations; h: h_1..h_8.
+template <class R, bool GENR>
+__device__ __forceinline__ void collide_site(const Phys<R>& p, const Front<R>& s,
+                                             R* f, R* g, R* h) {
+  collide_fg<R, GENR>(p, s, f, g);
   collide_flow(h, s, p.s3h, p.s4h);
 }
 

@@ -15,6 +15,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+FLOWS = {"ns": 0, "prescribed": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp16dev": 2}
 EOS = {"linear": 0, "langmuir": 1}
 
@@ -33,7 +34,7 @@ class lbm_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("walls_y", ctypes.c_int32), ("eos", ctypes.c_int32),
-        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("flow", ctypes.c_int32),
         ("u_wall_bot", ctypes.c_double), ("u_wall_top", ctypes.c_double),
         ("phiA", ctypes.c_double), ("phiB", ctypes.c_double),
         ("W", ctypes.c_double), ("M", ctypes.c_double), ("D", ctypes.c_double),
@@ -145,7 +146,8 @@ def to_c_params(p: dict) -> lbm_params:
     c.eos = EOS[p.get("eos", "linear")] if isinstance(p.get("eos", "linear"), str) else int(p["eos"])
     prec = p.get("precision", "fp64")
     c.precision = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
-    c.reserved = 0
+    fl = p.get("flow", "ns")
+    c.flow = FLOWS[fl] if isinstance(fl, str) else int(fl)
     c.u_wall_bot = float(p.get("u_wall_bot", 0.0))
     c.u_wall_top = float(p.get("u_wall_top", 0.0))
     c.phiA = float(p.get("phiA", 1.0))

@@ -31,6 +31,8 @@ def mixed_problems():
     rng = np.random.default_rng(7)
     pr = W.c4_instance(rng, precision="fp32", steps=64)
     out.append((pr.params, pr.fields0, 64))
+    pr = W.e2_convection(nx=64, R=12.0, precision="fp32", steps=48)  # prescribed velocity
+    out.append((pr.params, pr.fields0, 48))
     return out
 
 
