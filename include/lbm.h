@@ -161,6 +161,29 @@ lbm_status lbm_read_fields(lbm_handle *h, double *phi, double *psi, double *ux,
  * LBM_ENONFINITE, LBM_EDEVICE. */
 lbm_status lbm_moments(lbm_handle *h, lbm_moments_t *out);
 
+/* Shape of fluid A at the current time level, float64, from the phase
+ * field phi (c = (phi - phi_B)/(phi_A - phi_B) is the fluid-A fraction):
+ * the quantities the paper follows for a sheared drop (interface length,
+ * Sec. 4.4) and the Taylor deformation.  For a domain holding one drop
+ * they describe that drop; with several drops, area and length are totals
+ * and the moments are those of all fluid A together. */
+typedef struct {
+  double area;          /* sum of c                                          */
+  double cx, cy;        /* centroid: circular mean along periodic directions,
+                           plain mean between walls (site units)             */
+  double Ixx, Ixy, Iyy; /* second moments of c about the centroid, / area,
+                           minimum-image displacements                       */
+  double length;        /* interface length: sum |grad phi| / (phi_A - phi_B),
+                           isotropic D2Q9 gradient                           */
+  double taylor_D;      /* (L - B)/(L + B), L, B = 2 sqrt(eigenvalues of I)  */
+  double angle;         /* major axis from +x, radians, in (-pi/2, pi/2]     */
+} lbm_shape_t;
+
+/* Shape diagnostics of the current level, reduced on the device in float64
+ * in a fixed order (synchronising).  EINVAL: out NULL or no fluid A;
+ * ESTATE / ENONFINITE as lbm_moments. */
+lbm_status lbm_shape(lbm_handle *h, lbm_shape_t *out);
+
 /* Checkpoint: the raw state (populations, previous level, step counter) in
  * storage precision.  lbm_state_bytes gives the size; lbm_get_state copies
  * it to host memory (synchronising), lbm_set_state restores it, after which
@@ -258,6 +281,9 @@ lbm_status lbm_batch_remaining(const lbm_batch *b, int32_t id, int64_t *remainin
 lbm_status lbm_batch_read_fields(lbm_batch *b, int32_t id, double *phi, double *psi,
                                  double *ux, double *uy, double *P);
 lbm_status lbm_batch_moments(lbm_batch *b, int32_t id, lbm_moments_t *out);
+
+/* As lbm_shape for simulation id (synchronising). */
+lbm_status lbm_batch_shape(lbm_batch *b, int32_t id, lbm_shape_t *out);
 
 /* Remove simulation id and return its workspace (synchronising). */
 lbm_status lbm_batch_retire(lbm_batch *b, int32_t id);

@@ -1320,6 +1320,71 @@ lbm_reduce_final_kernel(const double *partials, int nblocks, double *out) {
   out[j] = v;
 }
 
+// Shape diagnostics of fluid A from the float64 phi of scratch plane 0:
+// c = (phi - phiB)/(phiA - phiB).  Pass 1 sums c, c cos/sin of the periodic
+// angles of x and y, c y, and |grad phi|; pass 2 sums c dx^2, c dx dy,
+// c dy^2 about the centroid (minimum image along periodic directions).
+// Per-block partials in a fixed order, as in lbm_reduce_kernel.
+constexpr int kShapeVals = 7;
+template <int PASS>
+__global__ void __launch_bounds__(256)
+lbm_shape_kernel(const double *phi, int nx, int ny, int walls, double phiA, double phiB,
+                 double cx, double cy, double *partials) {
+  double acc[kShapeVals] = {0, 0, 0, 0, 0, 0, 0};
+  const long long n = (long long)nx * ny;
+  const double inv = 1.0 / (phiA - phiB);
+  const double tx = 2.0 * M_PI / nx, ty = 2.0 * M_PI / ny;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    const int x = int(k % nx), y = int(k / nx);
+    const double c = (phi[k] - phiB) * inv;
+    if (PASS == 1) {
+      const Nine<double> v = gather9<double>(
+          [&](int yy, int xx) { return phi[(long long)yy * nx + xx]; }, x, y, nx, ny, walls);
+      double gx, gy;
+      grad9(v, gx, gy);
+      acc[0] += c;
+      acc[1] += c * cos(tx * x);
+      acc[2] += c * sin(tx * x);
+      acc[3] += c * cos(ty * y);
+      acc[4] += c * sin(ty * y);
+      acc[5] += c * y;
+      acc[6] += sqrt(gx * gx + gy * gy);
+    } else {
+      double dx = x - cx;
+      dx -= nx * rint(dx / nx);
+      double dy = y - cy;
+      if (!walls) dy -= ny * rint(dy / ny);
+      acc[0] += c * dx * dx;
+      acc[1] += c * dx * dy;
+      acc[2] += c * dy * dy;
+    }
+  }
+  __shared__ double lds[kShapeVals][256 / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+  for (int j = 0; j < kShapeVals; ++j) {
+    const double v = wave_sum(acc[j]);
+    if (lane == 0) lds[j][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kShapeVals) {
+    const int j = threadIdx.x;
+    double v = lds[j][0];
+    for (int q = 1; q < 256 / kWave; ++q) v += lds[j][q];
+    partials[blockIdx.x * kShapeVals + j] = v;
+  }
+}
+
+// Sums of nvals partial columns over nblocks, in block order.
+__global__ void __launch_bounds__(64)
+lbm_sum_final_kernel(const double *partials, int nblocks, int nvals, double *out) {
+  if (int(threadIdx.x) >= nvals) return;
+  const int j = threadIdx.x;
+  double v = partials[j];
+  for (int b = 1; b < nblocks; ++b) v += partials[b * nvals + j];
+  out[j] = v;
+}
+
 // ------------------------------------------------------------------ host
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -1774,6 +1839,63 @@ lbm_status lbm_moments(lbm_handle *h, lbm_moments_t *out) {
     h->valid = false;
     return fail(h, LBM_ENONFINITE, "non-finite macroscopic field");
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_shape(lbm_handle *h, lbm_shape_t *out) {
+  if (!h) return LBM_EINVAL;
+  if (!out) return fail(h, LBM_EINVAL, "out is NULL");
+  if (!h->valid) return fail(h, LBM_ESTATE, "no valid state");
+  lbm_status st = check_flag(h);
+  if (st != LBM_OK) return st;
+  hipError_t e = run_macros(h);
+  if (e != hipSuccess) return hip_check(h, e, "launching read-back kernels");
+  const lbm_params &p = h->p;
+  const double *phi = scratch(h);
+  double *part = partials(h);
+  double *res = part + kReduceBlocks * kShapeVals;
+  auto pass = [&](int which, double cx, double cy, double *v) -> hipError_t {
+    if (which == 1)
+      hipLaunchKernelGGL(lbm_shape_kernel<1>, dim3(kReduceBlocks), dim3(256), 0, h->stream,
+                         phi, p.nx, p.ny, p.walls_y, p.phiA, p.phiB, cx, cy, part);
+    else
+      hipLaunchKernelGGL(lbm_shape_kernel<2>, dim3(kReduceBlocks), dim3(256), 0, h->stream,
+                         phi, p.nx, p.ny, p.walls_y, p.phiA, p.phiB, cx, cy, part);
+    hipLaunchKernelGGL(lbm_sum_final_kernel, dim3(1), dim3(64), 0, h->stream,
+                       (const double *)part, kReduceBlocks, kShapeVals, res);
+    hipError_t e2 = hipGetLastError();
+    if (e2 == hipSuccess)
+      e2 = hipMemcpyAsync(v, res, sizeof(double) * kShapeVals, hipMemcpyDeviceToHost, h->stream);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(h->stream);
+    return e2;
+  };
+  double s1[kShapeVals], s2[kShapeVals];
+  e = pass(1, 0.0, 0.0, s1);
+  if (e != hipSuccess) return hip_check(h, e, "shape pass 1");
+  const double area = s1[0];
+  if (!(area > 0.0)) return fail(h, LBM_EINVAL, "no fluid A in the domain");
+  auto circ = [](double c, double s, int n) {
+    double a = std::atan2(s, c) * n / (2.0 * M_PI);
+    a = std::fmod(a, double(n));
+    return a < 0 ? a + n : a;
+  };
+  const double cx = circ(s1[1], s1[2], p.nx);
+  const double cy = p.walls_y ? s1[5] / area : circ(s1[3], s1[4], p.ny);
+  e = pass(2, cx, cy, s2);
+  if (e != hipSuccess) return hip_check(h, e, "shape pass 2");
+  const double ixx = s2[0] / area, ixy = s2[1] / area, iyy = s2[2] / area;
+  const double tr = ixx + iyy, det = ixx * iyy - ixy * ixy;
+  const double disc = std::sqrt(std::max(tr * tr / 4 - det, 0.0));
+  const double L = 2 * std::sqrt(tr / 2 + disc), B = 2 * std::sqrt(std::max(tr / 2 - disc, 0.0));
+  out->area = area;
+  out->cx = cx;
+  out->cy = cy;
+  out->Ixx = ixx;
+  out->Ixy = ixy;
+  out->Iyy = iyy;
+  out->length = s1[6] / (p.phiA - p.phiB);
+  out->taylor_D = (L + B) > 0 ? (L - B) / (L + B) : 0.0;
+  out->angle = 0.5 * std::atan2(2 * ixy, ixx - iyy);
   return LBM_OK;
 }
 
@@ -2292,6 +2414,16 @@ lbm_status lbm_batch_moments(lbm_batch *b, int32_t id, lbm_moments_t *out) {
     return bfail(b, LBM_EINVAL, "unknown simulation id");
   lbm_handle *h = b->inst[id].h;
   lbm_status st = lbm_moments(h, out);
+  if (st != LBM_OK) bfail(b, st, h->err);
+  return st;
+}
+
+lbm_status lbm_batch_shape(lbm_batch *b, int32_t id, lbm_shape_t *out) {
+  if (!b) return LBM_EINVAL;
+  if (id < 0 || id >= b->max_inst || !b->inst[id].h)
+    return bfail(b, LBM_EINVAL, "unknown simulation id");
+  lbm_handle *h = b->inst[id].h;
+  lbm_status st = lbm_shape(h, out);
   if (st != LBM_OK) bfail(b, st, h->err);
   return st;
 }

@@ -55,6 +55,11 @@ class lbm_moments_t(ctypes.Structure):
                 ("pad", ctypes.c_int32)]
 
 
+class lbm_shape_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("area", "cx", "cy", "Ixx", "Ixy", "Iyy", "length", "taylor_D", "angle")]
+
+
 class lbm_schedule(ctypes.Structure):
     """Tile-to-wavefront schedule of a batch (see include/lbm.h)."""
     _fields_ = [("rows", ctypes.c_int32), ("grid_waves", ctypes.c_int32),
@@ -126,6 +131,10 @@ def load(path: str = LIB_PATH):
     lib.lbm_batch_set_schedule.argtypes = [B, S]
     lib.lbm_batch_get_schedule.argtypes = [B, S]
     lib.lbm_batch_autotune.argtypes = [B, i64, S]
+    lib.lbm_shape.argtypes = [H, ctypes.POINTER(lbm_shape_t)]
+    lib.lbm_shape.restype = ctypes.c_int
+    lib.lbm_batch_shape.argtypes = [B, i32, ctypes.POINTER(lbm_shape_t)]
+    lib.lbm_batch_shape.restype = ctypes.c_int
     lib.lbm_batch_destroy.argtypes = [B]
     lib.lbm_batch_destroy.restype = None
     lib.lbm_batch_last_error.argtypes = [B]
@@ -231,6 +240,13 @@ class Simulation:
         m = lbm_moments_t()
         self._check(self.lib.lbm_moments(self._handle, ctypes.byref(m)))
         return {k: getattr(m, k) for k, _ in lbm_moments_t._fields_ if k != "pad"}
+
+    def shape(self) -> dict:
+        """Shape diagnostics of fluid A (area, centroid, moments, interface
+        length, Taylor deformation, orientation), reduced on the device."""
+        sh = lbm_shape_t()
+        self._check(self.lib.lbm_shape(self._handle, ctypes.byref(sh)))
+        return {k: getattr(sh, k) for k, _ in lbm_shape_t._fields_}
 
     def state_bytes(self) -> int:
         return int(self.lib.lbm_state_bytes(self._handle))
@@ -352,6 +368,11 @@ class Batch:
         m = lbm_moments_t()
         self._check(self.lib.lbm_batch_moments(self._b, int(i), ctypes.byref(m)))
         return {k: getattr(m, k) for k, _ in lbm_moments_t._fields_ if k != "pad"}
+
+    def shape(self, i: int) -> dict:
+        sh = lbm_shape_t()
+        self._check(self.lib.lbm_batch_shape(self._b, int(i), ctypes.byref(sh)))
+        return {k: getattr(sh, k) for k, _ in lbm_shape_t._fields_}
 
     def retire(self, i: int):
         self._check(self.lib.lbm_batch_retire(self._b, int(i)))

@@ -279,3 +279,27 @@ def test_prescribed_random_small_fp64(seed):
     want = ref.fields()
     check(got, want, 1e-12, f"prescribed random{seed} {params['nx']}x{params['ny']} "
           f"walls={params['walls_y']} r={params['r']}")
+
+
+# ------------------------------------------------ shape diagnostics
+
+def test_shape_diagnostics_match_the_oracle():
+    """lbm_shape (device float64 reductions) against the plain numpy
+    diagnostics: on the library's own read-back phi (same input: the
+    reductions alone) and on the oracle's phi of the same run."""
+    import shape as SH
+
+    pr = W.c2_shear_drop(beta=0.5)
+    sim = lbm.Simulation(dict(pr.params, precision="fp64"))
+    sim.init_fields(*pr.fields0)
+    sim.step(300)
+    got = sim.shape()
+    mine = SH.shape(sim.read_fields()["phi"], pr.params)
+    _, want_f = run_oracle(pr, 300)
+    want = SH.shape(want_f["phi"], pr.params)
+    for k in mine:
+        scale = max(abs(mine[k]), 1.0)
+        assert abs(got[k] - mine[k]) <= 1e-12 * scale, (k, got[k], mine[k])
+        assert abs(got[k] - want[k]) <= 1e-10 * scale, (k, got[k], want[k])
+    assert 0.0 < got["taylor_D"] < 0.5 and got["length"] > 2 * np.pi * 32 * 0.95
+    sim.close()
