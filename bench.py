@@ -186,7 +186,7 @@ def rel_errors(got, want):
 
 
 def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), load=0.7,
-                  max_steps=20000):
+                  max_steps=20000, quiet=False):
     """The serving stream: Poisson arrivals of drop-in-shear and Marangoni
     migration solves (sites log-uniform in [128^2, 1024^2], steps uniform in
     [1000, max_steps]) at `load` times the batch's measured capacity,
@@ -253,8 +253,14 @@ def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), loa
                             offered_rate_per_s=round(rate, 3), fp64_rerun_checked=len(errs),
                             worst_rel_err_vs_fp64=worst,
                             fp64_spread_from_perturbation_1e10=wsp))
-            print(json.dumps({"serving_run": out[-1]}), file=sys.stderr, flush=True)
+            if not quiet:
+                print(json.dumps({"serving_run": out[-1]}), file=sys.stderr, flush=True)
     return out
+
+
+def progress(msg: str):
+    """Phase marker on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -272,6 +278,8 @@ def main():
                     help="the serving stream (p50/p99 latency) instead of the 2048^2 field")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-max-steps", type=int, default=20000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the short batched-sweep and serving runs of the default line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -366,8 +374,21 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    progress(f"2048x2048 field: {mlups:.0f} MLUPS")
+    if not args.no_extras:
+        # the batched sweep (256 problems) and a short serving stream, so the
+        # one line carries every figure of the metric
+        out["batched"] = batched_sweep(steps=400)
+        progress(f"batched sweep: {out['batched']['batched_tuned_MLUPS']} MLUPS")
+        runs = serving_bench(n=60, budgets_gb=(64,), precisions=("fp32",), max_steps=5000,
+                             quiet=True)
+        out["serving"] = runs[0]
+        out["latency_p50_s"] = runs[0]["latency_p50_s"]
+        out["latency_p99_s"] = runs[0]["latency_p99_s"]
+        progress(f"serving stream: p50 {runs[0]['latency_p50_s']} s, p99 {runs[0]['latency_p99_s']} s")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 
