@@ -258,6 +258,65 @@ def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), loa
     return out
 
 
+def precision_run(steps=5000):
+    """The 2048x2048 field advanced `steps` steps in float32 and
+    float16-deviation storage, compared with the float64 library run (the
+    reference for long runs once float64 matches the oracle to 1e-12), and
+    the drift of Sum phi, Sum psi in each."""
+    import torch
+
+    from paper_2408_15654_amd import lbm, workloads
+
+    pr = workloads.c3_many_drops()
+    res, ref = {}, None
+    for prec in ("fp64", "fp32", "fp16dev"):
+        sim = lbm.Simulation(dict(pr.params, precision=prec))
+        sim.init_fields(*pr.fields0)
+        m0 = sim.moments()
+        sim.step(steps)
+        f = sim.read_fields()
+        m1 = sim.moments()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        drift = {"sum_phi": (m1["sum_phi"] - m0["sum_phi"]) / m0["sum_phi"],
+                 "sum_psi": (m1["sum_psi"] - m0["sum_psi"]) / m0["sum_psi"]}
+        if ref is None:
+            ref = f
+            res[prec] = {"drift": drift}
+        else:
+            res[prec] = {"rel_err_vs_fp64": rel_errors(f, ref), "drift": drift}
+    return {"steps": steps, **res}
+
+
+def shear_run(steps=20000, every=2500):
+    """The 256x128 drop in shear (beta 0 and 0.5) in float64 and float32:
+    Taylor deformation D(t) and interface length from the on-device shape
+    diagnostics, and the drift of Sum psi."""
+    from paper_2408_15654_amd import lbm, workloads
+
+    out = {}
+    for beta in (0.0, 0.5):
+        pr = workloads.c2_shear_drop(beta=beta)
+        for prec in ("fp64", "fp32"):
+            sim = lbm.Simulation(dict(pr.params, precision=prec))
+            sim.init_fields(*pr.fields0)
+            m0 = sim.moments()
+            D, C = [], []
+            for t in range(0, steps + 1, every):
+                if t:
+                    sim.step(every)
+                sh = sim.shape()
+                D.append(round(sh["taylor_D"], 6))
+                C.append(round(sh["length"], 3))
+            m1 = sim.moments()
+            sim.close()
+            out[f"beta{beta}_{prec}"] = {
+                "t": list(range(0, steps + 1, every)), "taylor_D": D, "length": C,
+                "sum_psi_drift": (m1["sum_psi"] - m0["sum_psi"]) / m0["sum_psi"]}
+    return out
+
+
 def progress(msg: str):
     """Phase marker on stderr (the JSON line alone goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -386,6 +445,10 @@ def main():
         out["latency_p50_s"] = runs[0]["latency_p50_s"]
         out["latency_p99_s"] = runs[0]["latency_p99_s"]
         progress(f"serving stream: p50 {runs[0]['latency_p50_s']} s, p99 {runs[0]['latency_p99_s']} s")
+        out["precision_2048_5000_steps"] = precision_run()
+        progress("precision run done")
+        out["shear_drop_20000_steps"] = shear_run()
+        progress("shear run done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr)
         progress("cpu baseline done")
