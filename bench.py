@@ -317,6 +317,33 @@ def shear_run(steps=20000, every=2500):
     return out
 
 
+def bubble_run(nx=240, precision="fp32", points=7):
+    """The rising bubble of Sec. 4.3 (240 x 480, t = 3, i.e. 172800 steps),
+    clean (E_0 = 0) and surfactant-laden (E_0 = 0.5): the bubble's centre
+    of mass Y_c (from the on-device shape diagnostics, in units of the
+    domain width) at `points` times."""
+    from paper_2408_15654_amd import lbm, workloads
+
+    out = {}
+    for beta in (0.0, 0.5):
+        pr = workloads.e3_rising_bubble(beta=beta, nx=nx, precision=precision)
+        sim = lbm.Simulation(pr.params)
+        sim.init_fields(*pr.fields0)
+        every = pr.steps // (points - 1)
+        ts, yc = [], []
+        t0 = time.perf_counter()
+        for k in range(points):
+            if k:
+                sim.step(every)
+            ts.append(round(k * every / nx ** 2, 4))
+            yc.append(round(sim.shape()["cy"] / nx, 5))
+        wall = time.perf_counter() - t0
+        sim.close()
+        out[f"E0_{beta}"] = {"t": ts, "Yc": yc, "steps": every * (points - 1),
+                             "seconds": round(wall, 2)}
+    return {"precision": precision, **out}
+
+
 def progress(msg: str):
     """Phase marker on stderr (the JSON line alone goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -449,6 +476,8 @@ def main():
         progress("precision run done")
         out["shear_drop_20000_steps"] = shear_run()
         progress("shear run done")
+        out["rising_bubble"] = bubble_run()
+        progress("rising bubble done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr)
         progress("cpu baseline done")

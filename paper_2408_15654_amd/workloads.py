@@ -298,6 +298,37 @@ def e2_convection(nx=100, R=20.0, u=(0.05, 0.0), steps=2000, r=1.0, precision="f
     return Problem("e2_convection", p, phi, phi.copy(), ux, uy, steps)
 
 
+def e3_rising_bubble(beta=0.0, nx=240, precision="fp32", steps=None, M=0.02, g=None,
+                     **kw) -> Problem:
+    """Sec. 4.3 in lattice units: domain [-2R,2R] x [0,8R], R = 0.25,
+    dx = 1/240, dt = dx^2 -> nx x 2nx with walls at the bottom and the top
+    (no slip) and periodic x; bubble R = nx/4 centred at (nx/2, nx/2).  The
+    bubble is fluid A here (phi = 1 inside), so the shape diagnostics give its
+    centre of mass Y_c.  Re = 2 rho R sqrt(2gR)/mu = 35, Bo = 4 rho g R^2 /
+    sigma0 = 10, Pe = 2R sqrt(2gR)/D = 10 with the heavy fluid's rho = 1,
+    density and viscosity ratios 10, sqrt(2gR) = 0.7 in units of the domain
+    width: nu = 0.01, g = 0.98 dx^3, D = 0.035.  psi from the unit-peak
+    profile with psi_0 = 1; linear EOS with E_0 = beta.  t = 3 -> 3 nx^2
+    steps.  M is not given in the paper (0.02 here)."""
+    dx = 1.0 / nx
+    R = nx / 4.0
+    nu = 0.01
+    g = 0.98 * dx ** 3 if g is None else g
+    rho_h, rho_b = 1.0, 0.1
+    mu_h, mu_b = nu * rho_h, nu * rho_b
+    sigma0 = 4 * rho_h * g * R * R / 10.0
+    D = 0.035
+    p = base_params(nx, 2 * nx, walls_y=1, W=4.0, M=M, D=D, r=1.0, rhoA=rho_b, rhoB=rho_h,
+                    muA=mu_b, muB=mu_h, sigma0=sigma0, beta=beta, gy=-g,
+                    precision=precision)
+    p.update(kw)
+    phi, _ = single_drop(nx, 2 * nx, R, cx=nx / 2.0, cy=nx / 2.0, W=4.0, periodic_y=False)
+    psi = unit_peak(phi)
+    z = np.zeros_like(phi)
+    return Problem(f"e3_bubble{nx}", p, phi, psi, z, z.copy(),
+                   3 * nx * nx if steps is None else steps)
+
+
 # ------------------------------------------------------- pin problems
 
 def e1_surface_diffusion(nx=100, R=25.0, steps=200) -> Problem:

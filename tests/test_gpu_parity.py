@@ -303,3 +303,14 @@ def test_shape_diagnostics_match_the_oracle():
         assert abs(got[k] - want[k]) <= 1e-10 * scale, (k, got[k], want[k])
     assert 0.0 < got["taylor_D"] < 0.5 and got["length"] > 2 * np.pi * 32 * 0.95
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rising_bubble_small(precision):
+    """Buoyant bubble between walls (Sec. 4.3 geometry, 40x80), 400 steps,
+    with surfactant (beta 0.5).  g = 5e-6: at g = 2e-5 this small problem
+    amplifies a 1e-15 perturbation to 1e-4 in the oracle alone."""
+    pr = W.e3_rising_bubble(nx=40, g=5e-6, steps=400, beta=0.5)
+    _, got = run_gpu(pr, precision, pr.steps)
+    _, want = run_oracle(pr, pr.steps)
+    check(got, want, TOL[precision], f"bubble40 {precision}")

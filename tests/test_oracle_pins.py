@@ -581,3 +581,26 @@ def test_prescribed_surfactant_relaxes_to_interface_profile(r, tol):
     unit = 4 * f["phi"] * (1 - f["phi"])
     c = q.psi0.sum() / unit.sum()
     assert np.abs(f["psi"] - c * unit).max() < tol * f["psi"].max()
+
+
+# ------------------------------------------------ buoyancy (Sec. 4.3)
+
+def test_light_bubble_rises_and_heavy_drop_sinks():
+    """Body force rho g (Sec. 4.3, between walls): a bubble ten times lighter
+    than its surroundings rises, the same drop made twice as heavy sinks; the
+    x-centroid stays on the symmetry line and Sum phi is conserved."""
+    import shape as SH
+
+    pr = W.e3_rising_bubble(nx=40, g=5e-6, steps=400)
+    y0 = SH.shape(pr.phi0, pr.params)["cy"]
+    s = O.OracleSim(pr.params, *pr.fields0)
+    s.step(400)
+    f = s.fields()
+    sh = SH.shape(f["phi"], pr.params)
+    assert sh["cy"] - y0 > 0.1, sh["cy"] - y0
+    assert abs(sh["cx"] - 20.0) < 1e-4  # mirror symmetry up to amplified rounding
+    assert abs(f["phi"].sum() / pr.phi0.sum() - 1) < 1e-12
+    heavy = W.e3_rising_bubble(nx=40, g=5e-6, steps=400, rhoA=2.0, muA=0.02)
+    s2 = O.OracleSim(heavy.params, *heavy.fields0)
+    s2.step(400)
+    assert SH.shape(s2.fields()["phi"], heavy.params)["cy"] - y0 < -0.05
