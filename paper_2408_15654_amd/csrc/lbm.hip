@@ -40,6 +40,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "lbm.h"
@@ -158,6 +159,18 @@ using rsrc_t = __amdgpu_buffer_rsrc_t;
 // writes is read again only by the next step, long after it has left the
 // caches; measured 1.6% faster than the default policy on the 2048x2048 field.
 constexpr int kStoreNT = 2;
+
+// Guards around a buffer store of more than 64 bits.  Such a store reads
+// its data registers over several cycles after it issues; measured on
+// gfx950, registers rewritten by the very next instructions (the compiler
+// leaves no gap when the store's offset is an SGPR) reached memory with
+// the new values in the last lanes of each 16-lane group.  The store is
+// pinned between two scheduling barriers and followed by two wait states.
+__device__ __forceinline__ void wide_store_begin() { __builtin_amdgcn_sched_barrier(0); }
+__device__ __forceinline__ void wide_store_guard() {
+  __asm__ volatile("s_nop 1" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes),
@@ -470,6 +483,52 @@ __device__ __forceinline__ double from_right(double v) {
                                           ((unsigned long long)(unsigned)hi << 32)));
 }
 
+// 3x3 neighbourhood of site k of a lane that holds K adjacent columns,
+// from the lane's values in rows y-1 (m), y (c), y+1 (n): neighbours
+// across the lane's edge come from the adjacent lanes.
+template <int K, int k, class R>
+__device__ __forceinline__ Nine<R> window_k(const R *m, const R *c, const R *n) {
+  Nine<R> v;
+  v.m = m[k];
+  v.c = c[k];
+  v.n = n[k];
+  if constexpr (k > 0) {
+    v.mL = m[k - 1];
+    v.cL = c[k - 1];
+    v.nL = n[k - 1];
+  } else {
+    v.mL = from_left(m[K - 1]);
+    v.cL = from_left(c[K - 1]);
+    v.nL = from_left(n[K - 1]);
+  }
+  if constexpr (k < K - 1) {
+    v.mR = m[k + 1];
+    v.cR = c[k + 1];
+    v.nR = n[k + 1];
+  } else {
+    v.mR = from_right(m[0]);
+    v.cR = from_right(c[0]);
+    v.nR = from_right(n[0]);
+  }
+  return v;
+}
+
+// Values of K adjacent columns pulled by one column to the right (sh = 1:
+// site k takes column k-1, site 0 the last column of the lane to the
+// left), to the left (sh = -1), or not at all (sh = 0).  sh is
+// wavefront-uniform; at wall rows the bounced populations are not shifted.
+template <int K, class R>
+__device__ __forceinline__ void shift_k(const R *v, int sh, R *out) {
+  R l[K], r[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    l[k] = k > 0 ? v[k > 0 ? k - 1 : 0] : from_left(v[K - 1]);
+    r[k] = k < K - 1 ? v[k < K - 1 ? k + 1 : 0] : from_right(v[0]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = sh > 0 ? l[k] : (sh < 0 ? r[k] : v[k]);
+}
+
 template <class R>
 __device__ __forceinline__ Nine<R> window(R m, R c, R n) {
   Nine<R> v;
@@ -524,7 +583,9 @@ struct PairIO<double> {
     w[1] = unsigned(__double2hiint(a));
     w[2] = unsigned(__double2loint(b));
     w[3] = unsigned(__double2hiint(b));
+    wide_store_begin();
     __builtin_amdgcn_raw_buffer_store_b128(w, r, v, s, kStoreNT);
+    wide_store_guard();
   }
 };
 template <>
@@ -545,7 +606,9 @@ struct PairIO<_Float16> {
   }
 };
 
-// Three floats through one 96-bit access.
+// Three floats: one 96-bit load; stored as 64 + 32 bits, so the store
+// needs no guard (the float16 path then keeps its stores unfenced and the
+// scheduler free to sink conversions past them).
 typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 struct TripleIO {
   static __device__ __forceinline__ void load(rsrc_t r, unsigned v, unsigned s, float &a,
@@ -558,11 +621,35 @@ struct TripleIO {
   }
   static __device__ __forceinline__ void store(float a, float b, float c, rsrc_t r, unsigned v,
                                                unsigned s) {
-    u32x3 w;
+    u32x2 w;
+    w[0] = __float_as_uint(a);
+    w[1] = __float_as_uint(b);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, v, s, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(c), r, v + 8, s, kStoreNT);
+  }
+};
+
+// Four floats through one 128-bit access.
+struct QuadIO {
+  static __device__ __forceinline__ void load(rsrc_t r, unsigned v, unsigned s, float &a,
+                                              float &b, float &c, float &d) {
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, v, s, 0);
+    const unsigned w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3];
+    a = __uint_as_float(w0);
+    b = __uint_as_float(w1);
+    c = __uint_as_float(w2);
+    d = __uint_as_float(w3);
+  }
+  static __device__ __forceinline__ void store(float a, float b, float c, float d, rsrc_t r,
+                                               unsigned v, unsigned s) {
+    u32x4 w;
     w[0] = __float_as_uint(a);
     w[1] = __float_as_uint(b);
     w[2] = __float_as_uint(c);
-    __builtin_amdgcn_raw_buffer_store_b96(w, r, v, s, kStoreNT);
+    w[3] = __float_as_uint(d);
+    wide_store_begin();
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, v, s, kStoreNT);
+    wide_store_guard();
   }
 };
 
@@ -661,51 +748,163 @@ __device__ __forceinline__ void wall_terms(bool bot, bool top, R rho_w, R uwb, R
   }
 }
 
-constexpr int kHalo = 2;                  // halo lanes on each side
-constexpr int kCols = kWave - 2 * kHalo;  // interior columns per wavefront
+// Strip geometry of the step kernel with K adjacent columns per lane: two
+// halo columns on each side (2 / K lanes), the rest interior.
+template <int K>
+struct Strip {
+  static constexpr int kHaloLanes = 2 / K;
+  static constexpr int kCols = K * (kWave - 2 * kHaloLanes);  // interior columns
+};
+
+// s_waitcnt operand (gfx9 encoding) that waits for all vector memory
+// operations only: vmcnt 0, expcnt and lgkmcnt at their maxima.
+constexpr int kWaitVmcnt0 = (0xF << 8) | (0x7 << 4);
 
 template <bool B>
 struct BoolC {
   static constexpr bool value = B;
 };
 
-// v on lanes where own is set, lane kHalo's v elsewhere (lane kHalo is an
-// interior lane of every strip).
+// f(std::integral_constant<int, k>) for k = 0 .. N-1, unrolled.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// v on lanes where own is set, lane L's v elsewhere (lane L is an interior
+// lane of every strip).
+template <int L>
 __device__ __forceinline__ unsigned lane_pick(bool own, unsigned v) {
-  const unsigned o = __builtin_amdgcn_readlane(v, kHalo);
+  const unsigned o = __builtin_amdgcn_readlane(v, L);
   return own ? v : o;
 }
+template <int L>
 __device__ __forceinline__ float lane_pick(bool own, float v) {
-  return __uint_as_float(lane_pick(own, __float_as_uint(v)));
+  return __uint_as_float(lane_pick<L>(own, __float_as_uint(v)));
 }
+template <int L>
 __device__ __forceinline__ double lane_pick(bool own, double v) {
-  const unsigned lo = lane_pick(own, unsigned(__double2loint(v)));
-  const unsigned hi = lane_pick(own, unsigned(__double2hiint(v)));
+  const unsigned lo = lane_pick<L>(own, unsigned(__double2loint(v)));
+  const unsigned hi = lane_pick<L>(own, unsigned(__double2hiint(v)));
   return __hiloint2double(int(hi), int(lo));
 }
 
+// Pull streaming with two adjacent columns per lane (float32 storage):
+// each population is loaded at the lane's own two columns, one 16-byte
+// (f, g) or 8-byte h access per plane (sources, bounce-back selection and
+// load order as in Pull).  The shift by c_ix is applied in registers by
+// shift_fg / shift_h when the row is used, not at the load, so the loads
+// of the next row stay in flight meanwhile.
+template <class P>
+struct Pull2 {
+  using R = typename P::R;
+  static_assert(!P::SCALED && sizeof(typename P::S) == 4, "float32 storage only");
+  static __device__ __forceinline__ void fg(rsrc_t rs, unsigned nxb, const RowOff &r,
+                                            unsigned col, R (*f)[9], R (*g)[9]) {
+    auto quad = [&](unsigned row, int i) {
+      QuadIO::load(rs, col, row, f[0][i], g[0][i], f[1][i], g[1][i]);
+    };
+    const bool bot = r.bot, top = r.top;
+    quad(r.c, 0);
+    quad(r.c + nxb, 1);
+    quad(r.c + 3 * nxb, 3);
+    quad(bot ? r.c + 4 * nxb : r.m + 2 * nxb, 2);
+    quad(bot ? r.c + 7 * nxb : r.m + 5 * nxb, 5);
+    quad(bot ? r.c + 8 * nxb : r.m + 6 * nxb, 6);
+    quad(top ? r.c + 2 * nxb : r.p + 4 * nxb, 4);
+    quad(top ? r.c + 5 * nxb : r.p + 7 * nxb, 7);
+    quad(top ? r.c + 6 * nxb : r.p + 8 * nxb, 8);
+  }
+  // shift of population i (1: from the left column, -1: from the right);
+  // populations bounced at a wall row come from the site itself
+  static __device__ __forceinline__ int shift_of(int i, bool bot, bool top) {
+    switch (i) {
+      case 1: return 1;
+      case 3: return -1;
+      case 5: return bot ? 0 : 1;
+      case 6: return bot ? 0 : -1;
+      case 7: return top ? 0 : -1;
+      case 8: return top ? 0 : 1;
+      default: return 0;
+    }
+  }
+  static __device__ __forceinline__ void shift_fg(bool bot, bool top, R (*f)[9], R (*g)[9]) {
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int sh = shift_of(i, bot, top);
+      if (i == 2 || i == 4) continue;
+      R a[2] = {f[0][i], f[1][i]}, b[2] = {g[0][i], g[1][i]}, oa[2], ob[2];
+      shift_k<2>(a, sh, oa);
+      shift_k<2>(b, sh, ob);
+      f[0][i] = oa[0];
+      f[1][i] = oa[1];
+      g[0][i] = ob[0];
+      g[1][i] = ob[1];
+    }
+  }
+  static __device__ __forceinline__ void h(rsrc_t rs, unsigned hb, unsigned nxh,
+                                           const RowOff &r, unsigned col, R (*out)[8]) {
+    auto two = [&](unsigned off, int k) {
+      PairIO<float>::load(rs, col, off + hb, out[0][k], out[1][k]);
+    };
+    const bool bot = r.bot, top = r.top;
+    two(r.c, 0);                                   // h_1
+    two(r.c + 2 * nxh, 2);                         // h_3
+    two(bot ? r.c + 3 * nxh : r.m + nxh, 1);       // h_2
+    two(bot ? r.c + 6 * nxh : r.m + 4 * nxh, 4);   // h_5
+    two(bot ? r.c + 7 * nxh : r.m + 5 * nxh, 5);   // h_6
+    two(top ? r.c + nxh : r.p + 3 * nxh, 3);       // h_4
+    two(top ? r.c + 4 * nxh : r.p + 6 * nxh, 6);   // h_7
+    two(top ? r.c + 5 * nxh : r.p + 7 * nxh, 7);   // h_8
+  }
+  // h[k] = h_{k+1}
+  static __device__ __forceinline__ void shift_h(bool bot, bool top, R (*h)[8]) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (k == 1 || k == 3) continue;
+      const int sh = shift_of(k + 1, bot, top);
+      R a[2] = {h[0][k], h[1][k]}, o[2];
+      shift_k<2>(a, sh, o);
+      h[0][k] = o[0];
+      h[1][k] = o[1];
+    }
+  }
+};
+
 // The fused step: pull-stream + boundaries, phi/psi/sigma, stencils, forces,
-// closures, three MRT collisions, store.  Lanes 0-1 and w+2, w+3 are halo
-// columns: they rebuild phi, psi, sigma for the stencils of the interior
-// lanes 2..w+1 but store nothing (lanes 0 and w+3 only serve lanes 1 and
-// w+2, whose rebuild needs the old rest values one column further out).
+// closures, three MRT collisions, store.  Each lane holds K adjacent
+// columns.  The two columns on each side of the interior are halo: they
+// rebuild phi, psi, sigma for the stencils of the interior columns but
+// store nothing (the outermost one only serves the rebuild of the next,
+// which needs the old rest values one column further out).
 // The row loop is software-pipelined: the loads for row y+1 are issued
 // before the arithmetic and stores of row y.
 // One tile (strip x rows) of one simulation, executed by one wavefront.
 // NS: velocity from the Navier-Stokes LB (h); otherwise prescribed (u held
 // in aux slots 0, 1; only f and g evolve).
-template <class P, bool GENR, bool HAS_S, bool NS>
+// K = 2 (float32 storage, even nx): every access of a lane covers two
+// sites, 16 bytes per (f, g) plane and 8 per h plane.
+template <class P, int K, bool GENR, bool HAS_S, bool NS>
 __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
                                           const int chunk) {
   using R = typename P::R;
   using S = typename P::S;
   using A = typename P::A;
+  static_assert(K == 1 || (K == 2 && !P::HDEV && !P::SCALED && sizeof(S) == 4 &&
+                           sizeof(A) == 4 && P::kRest == 2 && P::kAux == 4),
+                "two columns per lane: float32 storage only");
+  constexpr int HL = Strip<K>::kHaloLanes;
+  constexpr int COLS = Strip<K>::kCols;
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = a.nx, ny = a.ny, walls = a.walls;
-  const int x0 = strip * kCols;
-  const int w = min(kCols, nx - x0);
-  const bool interior = lane >= kHalo && lane < kHalo + w;
-  int xl = x0 - kHalo + min(lane, w + 2 * kHalo - 1);
+  const int x0 = strip * COLS;
+  const int wl = min(COLS, nx - x0) / K;  // interior lanes (nx is a multiple of K)
+  const bool interior = lane >= HL && lane < HL + wl;
+  int xl = x0 - K * HL + K * min(lane, wl + 2 * HL - 1);  // first column of the lane
   xl %= nx;
   if (xl < 0) xl += nx;
   const unsigned xc = unsigned(xl);
@@ -719,8 +918,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   co.h0 = xc * ES;
   co.hm = xcm * ES;
   co.hp = xcp * ES;
-  const unsigned brest = xc * P::kRest * EA;  // this site's rest record in a row
-  const unsigned baux = xc * P::kAux * EA;    // this site's aux record
+  const unsigned brest = xc * P::kRest * EA;  // this lane's first rest record in a row
+  const unsigned baux = xc * P::kAux * EA;    // this lane's first aux record
   const int y0 = chunk * a.rows;
   const int y1 = min(y0 + a.rows, ny);
   const unsigned nsites = unsigned(nx) * unsigned(ny);
@@ -737,35 +936,60 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   const rsrc_t raux = make_rsrc(a.aux, unsigned(P::kAux) * nsites * EA);
   const Phys<R> &p = a.p;
   const Scales<P> &sc = a.sc;
+  // float32 aux records read and written whole (one guarded 16-byte access)
+  constexpr bool kAuxQuad = sizeof(A) == 4 && P::kAux == 4 && HAS_S && NS;
 
-  // old (phi, psi) of this column at row y, wrapped or clamped
-  auto rest_at = [&](int y, R &X, R &Y) {
-    A u, v;
-    PairIO<A>::load(rrest, brest, unsigned(wrap_row(y, ny, walls)) * rrow, u, v);
-    X = R(u);
-    Y = R(v);
+  // old (phi, psi) of this lane's columns at row y, wrapped or clamped
+  auto rest_at = [&](int y, R *X, R *Y) {
+    const unsigned ro = unsigned(wrap_row(y, ny, walls)) * rrow;
+    if constexpr (K == 1) {
+      A u, v;
+      PairIO<A>::load(rrest, brest, ro, u, v);
+      X[0] = R(u);
+      Y[0] = R(v);
+    } else {
+      QuadIO::load(rrest, brest, ro, X[0], Y[0], X[1], Y[1]);
+    }
   };
   // raw stored deviations of f and g pulled to row r
-  auto load_fg = [&](int r, R *d, R *q) {
-    Pull<P>::fg(rsrc, nxb, row_offsets(r, ny, walls, rows_s), co, sc, d, q);
+  auto load_fg = [&](int r, R (*d)[9], R (*q)[9]) {
+    const RowOff o = row_offsets(r, ny, walls, rows_s);
+    if constexpr (K == 1)
+      Pull<P>::fg(rsrc, nxb, o, co, sc, d[0], q[0]);
+    else
+      Pull2<P>::fg(rsrc, nxb, o, co.p0, d, q);
   };
   // loads of row y that the rebuild of row y+1 does not need
-  auto load_row = [&](int y, R *h, R &uxp, R &uyp, R &Sxp, R &Syp) {
-    if constexpr (NS) Pull<P>::h(rsrc, hb, nxh, row_offsets(y, ny, walls, rows_s), co, sc.hi, h);
-    A u, v;
-    if constexpr (!P::HDEV || !NS) {  // u: previous level, or the prescribed field
-      PairIO<A>::load(raux, baux, unsigned(y) * arow, u, v);
-      uxp = R(u);
-      uyp = R(v);
-    } else {  // from the rest record (P, rho u) instead
-      uxp = uyp = R(0);
+  auto load_row = [&](int y, R (*h)[8], R *uxp, R *uyp, R *Sxp, R *Syp) {
+    if constexpr (NS) {
+      const RowOff o = row_offsets(y, ny, walls, rows_s);
+      if constexpr (K == 1)
+        Pull<P>::h(rsrc, hb, nxh, o, co, sc.hi, h[0]);
+      else
+        Pull2<P>::h(rsrc, hb, nxh, o, co.h0, h);
     }
-    if (HAS_S && NS) {
-      PairIO<A>::load(raux, baux + P::kAuxS * EA, unsigned(y) * arow, u, v);
-      Sxp = R(u);
-      Syp = R(v);
-    } else {
-      Sxp = Syp = R(0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const unsigned bk = baux + unsigned(k) * P::kAux * EA;
+      if constexpr (kAuxQuad) {  // (ux, uy, Sx, Sy) in one access
+        QuadIO::load(raux, bk, unsigned(y) * arow, uxp[k], uyp[k], Sxp[k], Syp[k]);
+      } else {
+        A u, v;
+        if constexpr (!P::HDEV || !NS) {  // u: previous level, or the prescribed field
+          PairIO<A>::load(raux, bk, unsigned(y) * arow, u, v);
+          uxp[k] = R(u);
+          uyp[k] = R(v);
+        } else {  // from the rest record (P, rho u) instead
+          uxp[k] = uyp[k] = R(0);
+        }
+        if (HAS_S && NS) {
+          PairIO<A>::load(raux, bk + P::kAuxS * EA, unsigned(y) * arow, u, v);
+          Sxp[k] = R(u);
+          Syp[k] = R(v);
+        } else {
+          Sxp[k] = Syp[k] = R(0);
+        }
+      }
     }
   };
   // old (P, rho ux, rho uy) of this column at row y (float16 storage only)
@@ -776,35 +1000,43 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   };
   // rebuild row r from its raw deviations: new phi, psi, sigma, and the
   // deviations relative to them (in place), given the old rest fields at
-  // rows r-1, r, r+1 of this column
-  auto rebuild = [&](int r, R Xm, R Xc, R Xn, R Ym, R Yc, R Yn, R *d, R *q, R &ph, R &ps,
-                     R &sg) {
+  // rows r-1, r, r+1 of the lane's columns
+  auto rebuild = [&](int r, const R *Xm, const R *Xc, const R *Xn, const R *Ym, const R *Yc,
+                     const R *Yn, R (*d)[9], R (*q)[9], R *ph, R *ps, R *sg) {
     const bool bot = walls && r == 0, top = walls && r == ny - 1;
-    R e[9];
-    source_offsets(window(Xm, Xc, Xn), bot, top, e);
-    ph = restream(d, e, Xc);
-    source_offsets(window(Ym, Yc, Yn), bot, top, e);
-    ps = restream(q, e, Yc);
-    sg = sigma_of(p, ps);
+    if constexpr (K == 2) Pull2<P>::shift_fg(bot, top, d, q);
+    static_for<K>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      R e[9];
+      source_offsets(window_k<K, k>(Xm, Xc, Xn), bot, top, e);
+      ph[k] = restream(d[k], e, Xc[k]);
+      source_offsets(window_k<K, k>(Ym, Yc, Yn), bot, top, e);
+      ps[k] = restream(q[k], e, Yc[k]);
+      sg[k] = sigma_of(p, ps[k]);
+    });
   };
   auto wrap_y = [&](int y) { return y >= ny ? y - ny : y; };
+  auto copy = [](R *dst, const R *src) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) dst[k] = src[k];
+  };
 
-  // old rest values of this column, rows y-1 .. y+2
-  R X0, X1, X2, X3, Y0, Y1, Y2, Y3;
+  // old rest values of this lane's columns, rows y-1 .. y+2
+  R X0[K], X1[K], X2[K], X3[K], Y0[K], Y1[K], Y2[K], Y3[K];
   rest_at(y0 - 1, X0, Y0);
   rest_at(y0, X1, Y1);
   rest_at(y0 + 1, X2, Y2);
   rest_at(y0 + 2, X3, Y3);
-  R dc[9], qc[9];
-  R phc, psc, sgc, phm, psm, sgm;
+  R dc[K][9], qc[K][9];
+  R phc[K], psc[K], sgc[K], phm[K], psm[K], sgm[K];
   load_fg(y0, dc, qc);
   rebuild(y0, X0, X1, X2, Y0, Y1, Y2, dc, qc, phc, psc, sgc);
   if (walls && y0 == 0) {  // mirror ghost row below the bottom wall
-    phm = phc;
-    psm = psc;
-    sgm = sgc;
+    copy(phm, phc);
+    copy(psm, psc);
+    copy(sgm, sgc);
   } else {
-    R dt[9], qt[9], Xa, Ya;
+    R dt[K][9], qt[K][9], Xa[K], Ya[K];
     const int ym = y0 == 0 ? ny - 1 : y0 - 1;
     rest_at(y0 - 2, Xa, Ya);
     load_fg(ym, dt, qt);
@@ -816,9 +1048,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   // memory operations on every path (no divergent or row-dependent branch
   // around a load or store), so the wait at the top of an iteration only
   // covers the loads it needs, not the stores just issued.
-  R dn[9], qn[9];  // raw deviations of row y+1
-  R hr[8];         // h of row y
-  R uxr, uyr, Sxr, Syr;
+  R dn[K][9], qn[K][9];  // raw deviations of row y+1
+  R hr[K][8];            // h of row y
+  R uxr[K], uyr[K], Sxr[K], Syr[K];
   // above the top wall the next row is the mirror ghost: the load of row
   // ny-1 keeps the sequence uniform and its values are not used
   auto next_fg_row = [&](int y) { return (walls && y >= ny) ? ny - 1 : wrap_y(y); };
@@ -832,46 +1064,59 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     hrest_at(y0 + 1, Hn);
   }
 
-  // Stores are issued by every lane: a halo lane repeats lane kHalo's value
-  // at lane kHalo's address (identical bits, same cache line).
-  const ColOff cs = {lane_pick(interior, co.p0), 0u, 0u, lane_pick(interior, co.h0), 0u, 0u};
-  const unsigned brest_s = lane_pick(interior, brest), baux_s = lane_pick(interior, baux);
+  // Stores are issued by every lane: a halo lane repeats lane HL's values
+  // at lane HL's address (identical bits, same cache line).
+  const ColOff cs = {lane_pick<HL>(interior, co.p0), 0u, 0u, lane_pick<HL>(interior, co.h0),
+                     0u, 0u};
+  const unsigned brest_s = lane_pick<HL>(interior, brest),
+                 baux_s = lane_pick<HL>(interior, baux);
+  auto lp = [&](R v) { return lane_pick<HL>(interior, v); };
   bool bad = false;
 
   auto row_step = [&](int y, auto prefetch) {
     // rebuild the next row from the raw deviations loaded last iteration
-    R phn, psn, sgn;
+    R phn[K], psn[K], sgn[K];
     const bool ghost = walls && y + 1 == ny;
     if (!ghost) {
       rebuild(wrap_y(y + 1), X1, X2, X3, Y1, Y2, Y3, dn, qn, phn, psn, sgn);
     } else {  // mirror ghost row above the top wall
-      phn = phc;
-      psn = psc;
-      sgn = sgc;
+      copy(phn, phc);
+      copy(psn, psc);
+      copy(sgn, sgc);
     }
-    R h[8];
+    R h[K][8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) h[i] = hr[i];
-    R uxp = uxr, uyp = uyr;
-    const R Sxp = Sxr, Syp = Syr;
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) h[k][i] = hr[k][i];
+    if constexpr (K == 2 && NS) Pull2<P>::shift_h(walls && y == 0, walls && y == ny - 1, h);
+    R uxp[K], uyp[K], Sxp[K], Syp[K];
+    copy(uxp, uxr);
+    copy(uyp, uyr);
+    copy(Sxp, Sxr);
+    copy(Syp, Syr);
     if constexpr (P::HDEV && NS) {  // add back the rest parts of the arriving h
       R b[8];
       h_arrival_basis(window(Hm.P, Hc.P, Hn.P), window(Hm.jx, Hc.jx, Hn.jx),
                       window(Hm.jy, Hc.jy, Hn.jy), walls && y == 0, walls && y == ny - 1, b);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) h[i] += b[i];
-      const R irho = R(1) / rho_of(p, X1);
-      uxp = Hc.jx * irho;
-      uyp = Hc.jy * irho;
+      for (int i = 0; i < 8; ++i) h[0][i] += b[i];
+      const R irho = R(1) / rho_of(p, X1[0]);
+      uxp[0] = Hc.jx * irho;
+      uyp[0] = Hc.jy * irho;
     }
-    R dnn[9], qnn[9];
+    R dnn[K][9], qnn[K][9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      dnn[i] = dn[i];
-      qnn[i] = qn[i];
-    }
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        dnn[k][i] = dn[k][i];
+        qnn[k][i] = qn[k][i];
+      }
 
-    R X4 = X3, Y4 = Y3;
+    R X4[K], Y4[K];
+    copy(X4, X3);
+    copy(Y4, Y3);
     if constexpr (decltype(prefetch)::value) {
       rest_at(y + 3, X4, Y4);
       load_fg(next_fg_row(y + 2), dn, qn);
@@ -879,92 +1124,131 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       hrest_at(y + 2, Hq);
     }
 
-    const R php = X1, psp = Y1;
     const bool bot = walls && y == 0, top = walls && y == ny - 1;
-    if constexpr (NS) wall_terms(bot, top, rho_of(p, php), p.uwb, p.uwt, h);
+    R oux[K], ouy[K], oSx[K], oSy[K];
+    HRest<R> hn{};
+    static_for<K>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const R php = X1[k], psp = Y1[k];
+      if constexpr (NS) wall_terms(bot, top, rho_of(p, php), p.uwb, p.uwt, h[k]);
 
-    // stencils from the register window
-    const Nine<R> vphi = window(phm, phc, phn);
-    const Nine<R> vsig = window(sgm, sgc, sgn);
-    R gfx, gfy, gsx, gsy;
-    grad9(vphi, gfx, gfy);
-    grad9(vsig, gsx, gsy);
-    const R lphi = lap9(vphi);
+      // stencils from the register window
+      const Nine<R> vphi = window_k<K, k>(phm, phc, phn);
+      const Nine<R> vsig = window_k<K, k>(sgm, sgc, sgn);
+      R gfx, gfy, gsx, gsy;
+      grad9(vphi, gfx, gfy);
+      grad9(vsig, gsx, gsy);
+      const R lphi = lap9(vphi);
 
-    Front<R> s;
-    if constexpr (NS)
-      site_front<R, HAS_S>(p, s, phc, psc, sgc, gfx, gfy, lphi, gsx, gsy, h, php, psp, uxp,
-                           uyp, Sxp, Syp);
-    else
-      site_front_prescribed<R>(p, s, phc, psc, gfx, gfy, uxp, uyp, php, psp);
-    if (GENR) {
-      const Nine<R> vpsi = window(psm, psc, psn);
-      grad9(vpsi, s.gpx, s.gpy);
-    } else {
-      s.gpx = s.gpy = R(0);
-    }
-    if constexpr (NS)
-      collide_site<R, GENR>(p, s, dc, qc, h);
-    else
-      collide_fg<R, GENR>(p, s, dc, qc);
+      Front<R> s;
+      if constexpr (NS)
+        site_front<R, HAS_S>(p, s, phc[k], psc[k], sgc[k], gfx, gfy, lphi, gsx, gsy, h[k], php,
+                             psp, uxp[k], uyp[k], Sxp[k], Syp[k]);
+      else
+        site_front_prescribed<R>(p, s, phc[k], psc[k], gfx, gfy, uxp[k], uyp[k], php, psp);
+      if (GENR) {
+        const Nine<R> vpsi = window_k<K, k>(psm, psc, psn);
+        grad9(vpsi, s.gpx, s.gpy);
+      } else {
+        s.gpx = s.gpy = R(0);
+      }
+      if constexpr (NS)
+        collide_site<R, GENR>(p, s, dc[k], qc[k], h[k]);
+      else
+        collide_fg<R, GENR>(p, s, dc[k], qc[k]);
+      if constexpr (P::HDEV && NS) {  // h as deviations from this site's new rest parts
+        hn = {s.P, s.jx, s.jy};
+        R b[8];
+        h_store_basis(hn, b);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) h[k][i] -= b[i];
+      }
+      oux[k] = s.ux;
+      ouy[k] = s.uy;
+      oSx[k] = s.Sx;
+      oSy[k] = s.Sy;
+      bad |= interior && !isfinite(phc[k] + psc[k] + s.ux + s.uy);
+    });
 
     const unsigned rcs = unsigned(y) * rows_s;
-    if constexpr (P::SCALED) {
+    if constexpr (K == 1) {
+      if constexpr (P::SCALED) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i)
-        PairIO<S>::store(S(lane_pick(interior, dc[i]) * sc.f), S(lane_pick(interior, qc[i]) * sc.g),
-                         rdst, cs.p0, rcs + unsigned(i) * nxb);
+        for (int i = 0; i < 9; ++i)
+          PairIO<S>::store(S(lp(dc[0][i]) * sc.f), S(lp(qc[0][i]) * sc.g), rdst, cs.p0,
+                           rcs + unsigned(i) * nxb);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          PairIO<S>::store(S(lp(dc[0][i])), S(lp(qc[0][i])), rdst, cs.p0,
+                           rcs + unsigned(i) * nxb);
+      }
+      if constexpr (NS) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          bst<P>(lp(h[0][i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh, sc.h);
+      }
+      PairIO<A>::store(A(lp(phc[0])), A(lp(psc[0])), rdrest, brest_s, unsigned(y) * rrow);
+      if constexpr (kAuxQuad) {
+        QuadIO::store(lp(oux[0]), lp(ouy[0]), lp(oSx[0]), lp(oSy[0]), raux, baux_s,
+                      unsigned(y) * arow);
+      } else {
+        if constexpr (P::HDEV && NS)
+          TripleIO::store(lp(hn.P), lp(hn.jx), lp(hn.jy), rdrest, brest_s + 2 * EA,
+                          unsigned(y) * rrow);
+        else if constexpr (NS)
+          PairIO<A>::store(A(lp(oux[0])), A(lp(ouy[0])), raux, baux_s, unsigned(y) * arow);
+        if (HAS_S && NS)
+          PairIO<A>::store(A(lp(oSx[0])), A(lp(oSy[0])), raux, baux_s + P::kAuxS * EA,
+                           unsigned(y) * arow);
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        PairIO<S>::store(S(lane_pick(interior, dc[i])), S(lane_pick(interior, qc[i])), rdst,
-                         cs.p0, rcs + unsigned(i) * nxb);
-    }
-    if constexpr (P::HDEV && NS) {  // h as deviations from this site's new rest parts
-      const HRest<R> hn = {s.P, s.jx, s.jy};
-      R b[8];
-      h_store_basis(hn, b);
+        QuadIO::store(lp(dc[0][i]), lp(qc[0][i]), lp(dc[1][i]), lp(qc[1][i]), rdst, cs.p0,
+                      rcs + unsigned(i) * nxb);
+      if constexpr (NS) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) h[i] -= b[i];
-    }
-    if constexpr (NS) {
+        for (int i = 0; i < 8; ++i)
+          PairIO<S>::store(lp(h[0][i]), lp(h[1][i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh);
+      }
+      QuadIO::store(lp(phc[0]), lp(psc[0]), lp(phc[1]), lp(psc[1]), rdrest, brest_s,
+                    unsigned(y) * rrow);
+      if constexpr (NS) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        bst<P>(lane_pick(interior, h[i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh, sc.h);
+        for (int k = 0; k < K; ++k) {
+          const unsigned bk = baux_s + unsigned(k) * P::kAux * EA;
+          if constexpr (HAS_S)
+            QuadIO::store(lp(oux[k]), lp(ouy[k]), lp(oSx[k]), lp(oSy[k]), raux, bk,
+                          unsigned(y) * arow);
+          else
+            PairIO<A>::store(lp(oux[k]), lp(ouy[k]), raux, bk, unsigned(y) * arow);
+        }
+      }
     }
-    PairIO<A>::store(A(lane_pick(interior, phc)), A(lane_pick(interior, psc)), rdrest,
-                     brest_s, unsigned(y) * rrow);
-    if constexpr (P::HDEV && NS)
-      TripleIO::store(lane_pick(interior, s.P), lane_pick(interior, s.jx),
-                      lane_pick(interior, s.jy), rdrest, brest_s + 2 * EA, unsigned(y) * rrow);
-    else if constexpr (NS)
-      PairIO<A>::store(A(lane_pick(interior, s.ux)), A(lane_pick(interior, s.uy)), raux,
-                       baux_s, unsigned(y) * arow);
-    if (HAS_S && NS)
-      PairIO<A>::store(A(lane_pick(interior, s.Sx)), A(lane_pick(interior, s.Sy)), raux,
-                       baux_s + P::kAuxS * EA, unsigned(y) * arow);
-    bad |= interior && !isfinite(phc + psc + s.ux + s.uy);
 
     // slide the windows
-    phm = phc;
-    psm = psc;
-    sgm = sgc;
-    phc = phn;
-    psc = psn;
-    sgc = sgn;
+    copy(phm, phc);
+    copy(psm, psc);
+    copy(sgm, sgc);
+    copy(phc, phn);
+    copy(psc, psn);
+    copy(sgc, sgn);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      dc[i] = dnn[i];
-      qc[i] = qnn[i];
-    }
-    X0 = X1;
-    X1 = X2;
-    X2 = X3;
-    X3 = X4;
-    Y0 = Y1;
-    Y1 = Y2;
-    Y2 = Y3;
-    Y3 = Y4;
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        dc[k][i] = dnn[k][i];
+        qc[k][i] = qnn[k][i];
+      }
+    copy(X0, X1);
+    copy(X1, X2);
+    copy(X2, X3);
+    copy(X3, X4);
+    copy(Y0, Y1);
+    copy(Y1, Y2);
+    copy(Y2, Y3);
+    copy(Y3, Y4);
     if constexpr (P::HDEV && NS) {
       Hm = Hc;
       Hc = Hn;
@@ -972,6 +1256,11 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     }
   };
 
+  // The first row needs the loads just issued in any case.  Waiting for
+  // them here leaves nothing of the prologue in flight at the loop head,
+  // so the waits placed there serve only the previous iteration's loads
+  // (long complete) instead of also holding back on its stores.
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   for (int y = y0; y < y1 - 1; ++y) row_step(y, BoolC<true>{});
   row_step(y1 - 1, BoolC<false>{});  // the last row prefetches nothing
   if (bad) *a.flag = 1;
@@ -980,7 +1269,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
 // One time step of one simulation: one wavefront per tile, strip-major
 // (consecutive wavefronts take adjacent strips of the same rows, so each
 // row streams contiguously from memory).
-template <class P, bool GENR, bool HAS_S, bool NS>
+template <class P, int K, bool GENR, bool HAS_S, bool NS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
 lbm_step_kernel(const StepArgs<P> a) {
   // the wavefront index is the same on every lane: make it a scalar so all
@@ -988,7 +1277,7 @@ lbm_step_kernel(const StepArgs<P> a) {
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   const int tile = blockIdx.x * kWavesPerBlock + wave;
   if (tile >= a.ntiles) return;  // whole wavefronts only
-  step_tile<P, GENR, HAS_S, NS>(a, tile % a.nstrips, tile / a.nstrips);
+  step_tile<P, K, GENR, HAS_S, NS>(a, tile % a.nstrips, tile / a.nstrips);
 }
 
 // ------------------------------------------------------------ batched step
@@ -1021,7 +1310,7 @@ struct BatchInst {
 // device memory (scalar loads), so a captured graph stays valid when the
 // batch's membership changes between chunks.  Every wavefront leaves the
 // loop after at most ceil(ntiles / stride) tiles.
-template <class P, bool GENR, bool HAS_S, bool NS>
+template <class P, int K, bool GENR, bool HAS_S, bool NS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
 lbm_batch_step_kernel(const BatchInst<P> *insts, const TileRef *tiles, const int *ntiles,
                       int k) {
@@ -1034,7 +1323,7 @@ lbm_batch_step_kernel(const BatchInst<P> *insts, const TileRef *tiles, const int
         (const LBM_CONST BatchInst<P> *)(insts) + tr.inst;
     if (k >= bi->steps) continue;
     const StepArgs<P> a = bi->a[(bi->parity + k) & 1];
-    step_tile<P, GENR, HAS_S, NS>(a, tr.strip, tr.chunk);
+    step_tile<P, K, GENR, HAS_S, NS>(a, tr.strip, tr.chunk);
   }
 }
 
@@ -1595,20 +1884,32 @@ SiteArgs<P> site_args(lbm_handle *h) {
   return a;
 }
 
+// Columns per lane of the step kernel: two for float32 storage when nx is
+// even (each lane's pair of columns then never straddles the periodic
+// seam), else one.
+int sites_per_lane(const lbm_params &p) {
+  return p.precision == LBM_FP32 && p.nx % 2 == 0 ? 2 : 1;
+}
+int strips_of(const lbm_params &p) {
+  const int cols = sites_per_lane(p) == 2 ? Strip<2>::kCols : Strip<1>::kCols;
+  return (p.nx + cols - 1) / cols;
+}
+
 int default_rows(const lbm_params &p) {
-  const long long strips = (p.nx + kCols - 1) / kCols;
+  const long long strips = strips_of(p);
   // Many short tiles keep the wavefronts' start-up and drain phases
   // staggered; the two extra halo rows per tile are served mostly from
-  // cache.  Measured on 2048x2048: 3 rows for float32, 4 for float16 and
-  // float64 storage.
+  // cache.  Measured on 2048x2048: 2 rows for float32 with two columns per
+  // lane, 3 with one, 4 for float16 and float64 storage.
   const long long target = p.precision == LBM_FP32 ? 24576 : 16384;
+  const long long lo = sites_per_lane(p) == 2 ? 2 : 3;
   long long rows = strips * p.ny / target;
-  if (rows < 3) rows = 3;
+  if (rows < lo) rows = lo;
   if (rows > 64) rows = 64;
   return int(rows);
 }
 
-template <class P, bool GENR, bool HAS_S, bool NS>
+template <class P, int K, bool GENR, bool HAS_S, bool NS>
 hipError_t launch_step(lbm_handle *h) {
   StepArgs<P> a;
   a.p = make_phys<typename P::R>(h->p);
@@ -1622,29 +1923,34 @@ hipError_t launch_step(lbm_handle *h) {
   a.nx = h->p.nx;
   a.ny = h->p.ny;
   a.walls = h->p.walls_y;
-  a.nstrips = (h->p.nx + kCols - 1) / kCols;
+  a.nstrips = strips_of(h->p);
   a.rows = h->rows;
   a.ntiles = a.nstrips * ((h->p.ny + a.rows - 1) / a.rows);
   const int blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
-  hipLaunchKernelGGL((lbm_step_kernel<P, GENR, HAS_S, NS>), dim3(blocks),
+  hipLaunchKernelGGL((lbm_step_kernel<P, K, GENR, HAS_S, NS>), dim3(blocks),
                      dim3(kWave * kWavesPerBlock), 0, h->stream, a);
   return hipGetLastError();
 }
 
-template <class P>
+template <class P, int K>
 hipError_t launch_step_prec(lbm_handle *h) {
   if (!h->ns)
-    return h->genr ? launch_step<P, true, false, false>(h) : launch_step<P, false, false, false>(h);
+    return h->genr ? launch_step<P, K, true, false, false>(h)
+                   : launch_step<P, K, false, false, false>(h);
   if (h->genr)
-    return h->has_s ? launch_step<P, true, true, true>(h) : launch_step<P, true, false, true>(h);
-  return h->has_s ? launch_step<P, false, true, true>(h) : launch_step<P, false, false, true>(h);
+    return h->has_s ? launch_step<P, K, true, true, true>(h)
+                    : launch_step<P, K, true, false, true>(h);
+  return h->has_s ? launch_step<P, K, false, true, true>(h)
+                  : launch_step<P, K, false, false, true>(h);
 }
 
 hipError_t run_step(lbm_handle *h) {
   switch (h->p.precision) {
-    case LBM_FP64: return launch_step_prec<F64>(h);
-    case LBM_FP32: return launch_step_prec<F32>(h);
-    default: return launch_step_prec<F16>(h);
+    case LBM_FP64: return launch_step_prec<F64, 1>(h);
+    case LBM_FP32:
+      return sites_per_lane(h->p) == 2 ? launch_step_prec<F32, 2>(h)
+                                       : launch_step_prec<F32, 1>(h);
+    default: return launch_step_prec<F16, 1>(h);
   }
 }
 
@@ -1973,10 +2279,12 @@ namespace {
 
 
 // Kernel variants: storage precision x prescribed velocity x (r != 1) x
-// (rho_A != rho_B).
-constexpr int kClasses = 24;
+// (rho_A != rho_B); float32 storage with two columns per lane is a fourth
+// group after the three precisions.
+constexpr int kClasses = 32;
 int class_of(const lbm_handle *h) {
-  return int(h->p.precision) * 8 + (h->ns ? 0 : 4) + (h->genr ? 2 : 0) + (h->has_s ? 1 : 0);
+  const int group = sites_per_lane(h->p) == 2 ? 3 : int(h->p.precision);
+  return group * 8 + (h->ns ? 0 : 4) + (h->genr ? 2 : 0) + (h->has_s ? 1 : 0);
 }
 
 template <class P>
@@ -1994,7 +2302,7 @@ StepArgs<P> step_args(const lbm_handle *h, int cur) {
   a.nx = h->p.nx;
   a.ny = h->p.ny;
   a.walls = h->p.walls_y;
-  a.nstrips = (h->p.nx + kCols - 1) / kCols;
+  a.nstrips = strips_of(h->p);
   a.rows = h->rows;
   a.ntiles = a.nstrips * ((h->p.ny + a.rows - 1) / a.rows);
   return a;
@@ -2019,33 +2327,37 @@ void fill_desc(void *dst, const lbm_handle *h, int steps) {
   std::memcpy(dst, &d, sizeof d);
 }
 
-template <class P, bool GENR, bool HAS_S, bool NS>
+template <class P, int K, bool GENR, bool HAS_S, bool NS>
 void launch_batch(int blocks, hipStream_t st, const void *desc, const TileRef *tiles,
                   const int *count, int k) {
-  hipLaunchKernelGGL((lbm_batch_step_kernel<P, GENR, HAS_S, NS>), dim3(blocks),
+  hipLaunchKernelGGL((lbm_batch_step_kernel<P, K, GENR, HAS_S, NS>), dim3(blocks),
                      dim3(kWave * kWavesPerBlock), 0, st,
                      static_cast<const BatchInst<P> *>(desc), tiles, count, k);
 }
 
-template <class P>
+template <class P, int K>
 void launch_batch_prec(int c, int blocks, hipStream_t st, const void *desc,
                        const TileRef *tiles, const int *count, int k) {
   switch (c & 7) {
-    case 0: launch_batch<P, false, false, true>(blocks, st, desc, tiles, count, k); break;
-    case 1: launch_batch<P, false, true, true>(blocks, st, desc, tiles, count, k); break;
-    case 2: launch_batch<P, true, false, true>(blocks, st, desc, tiles, count, k); break;
-    case 3: launch_batch<P, true, true, true>(blocks, st, desc, tiles, count, k); break;
-    case 4: launch_batch<P, false, false, false>(blocks, st, desc, tiles, count, k); break;
-    default: launch_batch<P, true, false, false>(blocks, st, desc, tiles, count, k); break;
+    case 0: launch_batch<P, K, false, false, true>(blocks, st, desc, tiles, count, k); break;
+    case 1: launch_batch<P, K, false, true, true>(blocks, st, desc, tiles, count, k); break;
+    case 2: launch_batch<P, K, true, false, true>(blocks, st, desc, tiles, count, k); break;
+    case 3: launch_batch<P, K, true, true, true>(blocks, st, desc, tiles, count, k); break;
+    case 4: launch_batch<P, K, false, false, false>(blocks, st, desc, tiles, count, k); break;
+    default: launch_batch<P, K, true, false, false>(blocks, st, desc, tiles, count, k); break;
   }
 }
+
+// Storage precision of a kernel variant class (its descriptor array).
+int class_precision(int c) { return c / 8 == 3 ? int(LBM_FP32) : c / 8; }
 
 void launch_batch_class(int c, int blocks, hipStream_t st, const void *desc,
                         const TileRef *tiles, const int *count, int k) {
   switch (c / 8) {
-    case LBM_FP64: launch_batch_prec<F64>(c, blocks, st, desc, tiles, count, k); break;
-    case LBM_FP32: launch_batch_prec<F32>(c, blocks, st, desc, tiles, count, k); break;
-    default: launch_batch_prec<F16>(c, blocks, st, desc, tiles, count, k); break;
+    case LBM_FP64: launch_batch_prec<F64, 1>(c, blocks, st, desc, tiles, count, k); break;
+    case LBM_FP32: launch_batch_prec<F32, 1>(c, blocks, st, desc, tiles, count, k); break;
+    case LBM_FP16DEV: launch_batch_prec<F16, 1>(c, blocks, st, desc, tiles, count, k); break;
+    default: launch_batch_prec<F32, 2>(c, blocks, st, desc, tiles, count, k); break;
   }
 }
 
@@ -2117,7 +2429,7 @@ lbm_status rebuild_tiles(lbm_batch *b) {
     if (!in.h) continue;
     lbm_handle *h = in.h;
     h->rows = b->sched.rows > 0 ? b->sched.rows : default_rows(h->p);
-    const size_t strips = (h->p.nx + kCols - 1) / kCols;
+    const size_t strips = strips_of(h->p);
     total += strips * size_t((h->p.ny + h->rows - 1) / h->rows);
   }
   hipError_t e = hipStreamSynchronize(b->stream);  // staging and tiles idle
@@ -2150,7 +2462,7 @@ lbm_status rebuild_tiles(lbm_batch *b) {
     for (int id = 0; id < b->max_inst; ++id) {
       const lbm_handle *h = b->inst[id].h;
       if (!h || class_of(h) != c) continue;
-      const int strips = (h->p.nx + kCols - 1) / kCols;
+      const int strips = strips_of(h->p);
       const int chunks = (h->p.ny + h->rows - 1) / h->rows;
       for (int ch = 0; ch < chunks; ++ch)
         for (int st = 0; st < strips; ++st) b->h_tiles[n++] = TileRef{id, st, ch, 0};
@@ -2229,7 +2541,7 @@ lbm_status get_graph(lbm_batch *b, int K, hipGraphExec_t *out) {
   for (int k = 0; k < K; ++k)
     for (int c = 0; c < kClasses; ++c) {
       if (!b->class_n[c]) continue;
-      launch_batch_class(c, class_blocks(b, c), b->capture, b->d_desc[c / 8],
+      launch_batch_class(c, class_blocks(b, c), b->capture, b->d_desc[class_precision(c)],
                          b->d_tiles + b->class_off[c], b->d_count + c, k);
     }
   hipGraph_t g = nullptr;
