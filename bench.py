@@ -91,10 +91,36 @@ def cpu_baseline(pr, target_seconds=15.0):
     t0 = time.perf_counter()
     sim.step(n)
     dt = time.perf_counter() - t0
-    return {"value": round(pr.sites * n / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"FP64 oracle, same 2048x2048 many-drop problem, {n} steps "
-                      f"after 1 warm-up step ({dt:.1f} s)"}
+    cores = oracle.threads()
+    out = {"value": round(pr.sites * n / dt / 1e6, 3), "unit": "MLUPS",
+           "cores": cores, "kind": "oracle",
+           "sample": f"FP64 oracle, same 2048x2048 many-drop problem, {n} steps "
+                     f"after 1 warm-up step ({dt:.1f} s)"}
+    # one thread on one step of the same problem, and the full 64x64 drop
+    # (2000 steps) on all threads
+    try:
+        v1, dt1 = oracle.time_mlups(pr.params, pr.fields0, 1, threads=1)
+        out["one_thread_MLUPS"] = round(v1, 3)
+    finally:
+        oracle.lib().or_set_threads(cores)
+    from paper_2408_15654_amd import workloads
+    c1 = workloads.c1_stationary_drop()
+    vc1, dtc1 = oracle.time_mlups(c1.params, c1.fields0, c1.steps)
+    out["c1_full_MLUPS"] = round(vc1, 3)
+    out["c1_full_seconds"] = round(dtc1, 2)
+    out["cpu_model"] = cpu_model()
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def copy_calibration(device="cuda:0", nbytes=1 << 30):
