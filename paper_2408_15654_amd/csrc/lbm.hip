@@ -227,6 +227,7 @@ struct BufIO<_Float16> {
 template <class P>
 __device__ __forceinline__ typename P::R bld(rsrc_t r, unsigned v, unsigned s,
                                              typename P::R inv) {
+#pragma clang fp contract(off)
   using R = typename P::R;
   if constexpr (P::SCALED)
     return R(BufIO<typename P::S>::load(r, v, s)) * inv;
@@ -701,6 +702,7 @@ struct Pull {
                                             const ColOff &c, const Scales<P> &sc, R *f, R *g) {
     // nxb: bytes of one pair row (nx pairs)
     auto pair = [&](int dir, unsigned row, unsigned col, int i) {
+#pragma clang fp contract(off)
       S a, b;
       PairIO<S>::load(rs, col, row + unsigned(dir) * nxb, a, b);
       if constexpr (P::SCALED) {
@@ -808,20 +810,47 @@ __device__ __forceinline__ double lane_pick(bool own, double v) {
   return __hiloint2double(int(hi), int(lo));
 }
 
-// Pull streaming with two adjacent columns per lane (float32 storage):
-// each population is loaded at the lane's own two columns, one 16-byte
-// (f, g) or 8-byte h access per plane (sources, bounce-back selection and
-// load order as in Pull).  The shift by c_ix is applied in registers by
+// Float16 halves of a 32-bit word.
+__device__ __forceinline__ float half_lo(unsigned w) {
+  return float(__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu)));
+}
+__device__ __forceinline__ float half_hi(unsigned w) {
+  return float(__builtin_bit_cast(_Float16, (unsigned short)(w >> 16)));
+}
+__device__ __forceinline__ unsigned halves(float lo, float hi) {
+  const unsigned short a = __builtin_bit_cast(unsigned short, _Float16(lo)),
+                       b = __builtin_bit_cast(unsigned short, _Float16(hi));
+  return unsigned(a) | (unsigned(b) << 16);
+}
+
+// Pull streaming with two adjacent columns per lane (float32 storage, or
+// scaled float16 deviations): each population is loaded at the lane's own
+// two columns, one (f, g) access (16 bytes float32, 8 bytes float16) and
+// one h access (8 or 4 bytes) per plane; sources, bounce-back selection
+// and load order as in Pull.  The shift by c_ix is applied in registers by
 // shift_fg / shift_h when the row is used, not at the load, so the loads
-// of the next row stay in flight meanwhile.
+// of the next row stay in flight meanwhile.  Float16 words are kept packed
+// until then (decode_fg / decode_h): the prefetched row then holds half the
+// registers, and no conversion consumes a load early.
 template <class P>
 struct Pull2 {
   using R = typename P::R;
-  static_assert(!P::SCALED && sizeof(typename P::S) == 4, "float32 storage only");
+  using S = typename P::S;
+  static_assert((!P::SCALED && sizeof(S) == 4) || (P::SCALED && sizeof(S) == 2),
+                "float32 or scaled float16 storage");
   static __device__ __forceinline__ void fg(rsrc_t rs, unsigned nxb, const RowOff &r,
-                                            unsigned col, R (*f)[9], R (*g)[9]) {
+                                            unsigned col, const Scales<P> &sc, R (*f)[9],
+                                            R (*g)[9]) {
     auto quad = [&](unsigned row, int i) {
-      QuadIO::load(rs, col, row, f[0][i], g[0][i], f[1][i], g[1][i]);
+      if constexpr (sizeof(S) == 4) {
+        QuadIO::load(rs, col, row, f[0][i], g[0][i], f[1][i], g[1][i]);
+      } else {  // packed (f, g) words of the two columns, decoded in decode_fg
+        const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, col, row, 0);
+        const unsigned w0 = w[0], w1 = w[1];
+        f[0][i] = __uint_as_float(w0);
+        f[1][i] = __uint_as_float(w1);
+        g[0][i] = g[1][i] = R(0);
+      }
     };
     const bool bot = r.bot, top = r.top;
     quad(r.c, 0);
@@ -833,6 +862,34 @@ struct Pull2 {
     quad(top ? r.c + 2 * nxb : r.p + 4 * nxb, 4);
     quad(top ? r.c + 5 * nxb : r.p + 7 * nxb, 7);
     quad(top ? r.c + 6 * nxb : r.p + 8 * nxb, 8);
+  }
+  // float16 storage: unpack and scale what fg() loaded.  The scaled values
+  // are rounded here (no contraction into the sums that use them), so the
+  // result does not depend on which copy of the row code a site runs in.
+  static __device__ __forceinline__ void decode_fg(const Scales<P> &sc, R (*f)[9], R (*g)[9]) {
+#pragma clang fp contract(off)
+    if constexpr (sizeof(S) == 2) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const unsigned w0 = __float_as_uint(f[0][i]), w1 = __float_as_uint(f[1][i]);
+        f[0][i] = half_lo(w0) * sc.fi;
+        g[0][i] = half_hi(w0) * sc.gi;
+        f[1][i] = half_lo(w1) * sc.fi;
+        g[1][i] = half_hi(w1) * sc.gi;
+      }
+    }
+  }
+  // float16 storage: unpack and scale what h() loaded
+  static __device__ __forceinline__ void decode_h(R inv, R (*h)[8]) {
+#pragma clang fp contract(off)
+    if constexpr (sizeof(S) == 2) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const unsigned w = __float_as_uint(h[0][k]);
+        h[0][k] = half_lo(w) * inv;
+        h[1][k] = half_hi(w) * inv;
+      }
+    }
   }
   // shift of population i (1: from the left column, -1: from the right);
   // populations bounced at a wall row come from the site itself
@@ -862,9 +919,15 @@ struct Pull2 {
     }
   }
   static __device__ __forceinline__ void h(rsrc_t rs, unsigned hb, unsigned nxh,
-                                           const RowOff &r, unsigned col, R (*out)[8]) {
+                                           const RowOff &r, unsigned col, R inv, R (*out)[8]) {
     auto two = [&](unsigned off, int k) {
-      PairIO<float>::load(rs, col, off + hb, out[0][k], out[1][k]);
+      if constexpr (sizeof(S) == 4) {
+        PairIO<float>::load(rs, col, off + hb, out[0][k], out[1][k]);
+      } else {  // packed h word of the two columns, decoded in decode_h
+        const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(rs, col, off + hb, 0);
+        out[0][k] = __uint_as_float(w);
+        out[1][k] = R(0);
+      }
     };
     const bool bot = r.bot, top = r.top;
     two(r.c, 0);                                   // h_1
@@ -909,9 +972,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   using R = typename P::R;
   using S = typename P::S;
   using A = typename P::A;
-  static_assert(K == 1 || (K == 2 && !P::HDEV && !P::SCALED && sizeof(S) == 4 &&
-                           sizeof(A) == 4 && P::kRest == 2 && P::kAux == 4),
-                "two columns per lane: float32 storage only");
+  static_assert(K == 1 || (K == 2 && sizeof(A) == 4 &&
+                           ((!P::SCALED && sizeof(S) == 4) || (P::SCALED && sizeof(S) == 2))),
+                "two columns per lane: float32 or float16 storage");
   constexpr int HL = Strip<K>::kHaloLanes;
   constexpr int COLS = Strip<K>::kCols;
   const int lane = threadIdx.x & (kWave - 1);
@@ -957,13 +1020,16 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   // old (phi, psi) of this lane's columns at row y, wrapped or clamped
   auto rest_at = [&](int y, R *X, R *Y) {
     const unsigned ro = unsigned(wrap_row(y, ny, walls)) * rrow;
-    if constexpr (K == 1) {
-      A u, v;
-      PairIO<A>::load(rrest, brest, ro, u, v);
-      X[0] = R(u);
-      Y[0] = R(v);
-    } else {
+    if constexpr (K == 2 && P::kRest == 2) {  // both records in one access
       QuadIO::load(rrest, brest, ro, X[0], Y[0], X[1], Y[1]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        A u, v;
+        PairIO<A>::load(rrest, brest + unsigned(k) * P::kRest * EA, ro, u, v);
+        X[k] = R(u);
+        Y[k] = R(v);
+      }
     }
   };
   // raw stored deviations of f and g pulled to row r
@@ -972,7 +1038,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     if constexpr (K == 1)
       Pull<P>::fg(rsrc, nxb, o, co, sc, d[0], q[0]);
     else
-      Pull2<P>::fg(rsrc, nxb, o, co.p0, d, q);
+      Pull2<P>::fg(rsrc, nxb, o, co.p0, sc, d, q);
   };
   // loads of row y that the rebuild of row y+1 does not need
   auto load_row = [&](int y, R (*h)[8], R *uxp, R *uyp, R *Sxp, R *Syp) {
@@ -981,7 +1047,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       if constexpr (K == 1)
         Pull<P>::h(rsrc, hb, nxh, o, co, sc.hi, h[0]);
       else
-        Pull2<P>::h(rsrc, hb, nxh, o, co.h0, h);
+        Pull2<P>::h(rsrc, hb, nxh, o, co.h0, sc.hi, h);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -1007,11 +1073,18 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       }
     }
   };
-  // old (P, rho ux, rho uy) of this column at row y (float16 storage only)
-  auto hrest_at = [&](int y, HRest<R> &v) {
-    if constexpr (P::HDEV && NS)
-      TripleIO::load(rrest, brest + 2 * EA, unsigned(wrap_row(y, ny, walls)) * rrow, v.P, v.jx,
-                     v.jy);
+  // old (P, rho ux, rho uy) of this lane's columns at row y (float16
+  // storage only)
+  struct HR {
+    R pr[K], jx[K], jy[K];
+  };
+  auto hrest_at = [&](int y, HR &v) {
+    if constexpr (P::HDEV && NS) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        TripleIO::load(rrest, brest + unsigned(k) * P::kRest * EA + 2 * EA,
+                       unsigned(wrap_row(y, ny, walls)) * rrow, v.pr[k], v.jx[k], v.jy[k]);
+    }
   };
   // rebuild row r from its raw deviations: new phi, psi, sigma, and the
   // deviations relative to them (in place), given the old rest fields at
@@ -1019,7 +1092,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   auto rebuild = [&](int r, const R *Xm, const R *Xc, const R *Xn, const R *Ym, const R *Yc,
                      const R *Yn, R (*d)[9], R (*q)[9], R *ph, R *ps, R *sg) {
     const bool bot = walls && r == 0, top = walls && r == ny - 1;
-    if constexpr (K == 2) Pull2<P>::shift_fg(bot, top, d, q);
+    if constexpr (K == 2) {
+      Pull2<P>::decode_fg(sc, d, q);
+      Pull2<P>::shift_fg(bot, top, d, q);
+    }
     static_for<K>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       R e[9];
@@ -1072,7 +1148,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   load_fg(next_fg_row(y0 + 1), dn, qn);
   load_row(y0, hr, uxr, uyr, Sxr, Syr);
   // rest (P, rho u) of rows y-1, y, y+1 and the prefetched y+2
-  HRest<R> Hm{}, Hc{}, Hn{}, Hq{};
+  HR Hm{}, Hc{}, Hn{}, Hq{};
   if constexpr (P::HDEV && NS) {
     hrest_at(y0 - 1, Hm);
     hrest_at(y0, Hc);
@@ -1104,21 +1180,28 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int i = 0; i < 8; ++i) h[k][i] = hr[k][i];
-    if constexpr (K == 2 && NS) Pull2<P>::shift_h(walls && y == 0, walls && y == ny - 1, h);
+    if constexpr (K == 2 && NS) {
+      Pull2<P>::decode_h(sc.hi, h);
+      Pull2<P>::shift_h(walls && y == 0, walls && y == ny - 1, h);
+    }
     R uxp[K], uyp[K], Sxp[K], Syp[K];
     copy(uxp, uxr);
     copy(uyp, uyr);
     copy(Sxp, Sxr);
     copy(Syp, Syr);
     if constexpr (P::HDEV && NS) {  // add back the rest parts of the arriving h
-      R b[8];
-      h_arrival_basis(window(Hm.P, Hc.P, Hn.P), window(Hm.jx, Hc.jx, Hn.jx),
-                      window(Hm.jy, Hc.jy, Hn.jy), walls && y == 0, walls && y == ny - 1, b);
+      static_for<K>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        R b[8];
+        h_arrival_basis(window_k<K, k>(Hm.pr, Hc.pr, Hn.pr), window_k<K, k>(Hm.jx, Hc.jx, Hn.jx),
+                        window_k<K, k>(Hm.jy, Hc.jy, Hn.jy), walls && y == 0,
+                        walls && y == ny - 1, b);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) h[0][i] += b[i];
-      const R irho = R(1) / rho_of(p, X1[0]);
-      uxp[0] = Hc.jx * irho;
-      uyp[0] = Hc.jy * irho;
+        for (int i = 0; i < 8; ++i) h[k][i] += b[i];
+        const R irho = R(1) / rho_of(p, X1[k]);
+        uxp[k] = Hc.jx[k] * irho;
+        uyp[k] = Hc.jy[k] * irho;
+      });
     }
     R dnn[K][9], qnn[K][9];
 #pragma unroll
@@ -1141,7 +1224,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
 
     const bool bot = walls && y == 0, top = walls && y == ny - 1;
     R oux[K], ouy[K], oSx[K], oSy[K];
-    HRest<R> hn{};
+    HR hn{};
     static_for<K>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       const R php = X1[k], psp = Y1[k];
@@ -1172,9 +1255,11 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       else
         collide_fg<R, GENR>(p, s, dc[k], qc[k]);
       if constexpr (P::HDEV && NS) {  // h as deviations from this site's new rest parts
-        hn = {s.P, s.jx, s.jy};
+        hn.pr[k] = s.P;
+        hn.jx[k] = s.jx;
+        hn.jy[k] = s.jy;
         R b[8];
-        h_store_basis(hn, b);
+        h_store_basis(HRest<R>{s.P, s.jx, s.jy}, b);
 #pragma unroll
         for (int i = 0; i < 8; ++i) h[k][i] -= b[i];
       }
@@ -1207,12 +1292,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       PairIO<A>::template store<P::kStorePol>(
           A(lp(phc[0])), A(lp(psc[0])), rdrest, brest_s, unsigned(y) * rrow);
       if constexpr (kAuxQuad) {
-        QuadIO::store<P::kStorePol>(lp(oux[0]), lp(ouy[0]), lp(oSx[0]), lp(oSy[0]), raux, baux_s,
-                      unsigned(y) * arow);
+        QuadIO::store<P::kStorePol>(lp(oux[0]), lp(ouy[0]), lp(oSx[0]), lp(oSy[0]), raux,
+                                    baux_s, unsigned(y) * arow);
       } else {
         if constexpr (P::HDEV && NS)
-          TripleIO::store<P::kStorePol>(lp(hn.P), lp(hn.jx), lp(hn.jy), rdrest, brest_s + 2 * EA,
-                          unsigned(y) * rrow);
+          TripleIO::store<P::kStorePol>(lp(hn.pr[0]), lp(hn.jx[0]), lp(hn.jy[0]), rdrest,
+                                        brest_s + 2 * EA, unsigned(y) * rrow);
         else if constexpr (NS)
           PairIO<A>::template store<P::kStorePol>(
               A(lp(oux[0])), A(lp(ouy[0])), raux, baux_s, unsigned(y) * arow);
@@ -1221,7 +1306,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
               A(lp(oSx[0])), A(lp(oSy[0])), raux, baux_s + P::kAuxS * EA,
                            unsigned(y) * arow);
       }
-    } else {
+    } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
       for (int i = 0; i < 9; ++i)
         QuadIO::store<P::kStorePol>(lp(dc[0][i]), lp(qc[0][i]), lp(dc[1][i]), lp(qc[1][i]), rdst,
@@ -1232,19 +1317,53 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
           PairIO<S>::template store<P::kStorePol>(
               lp(h[0][i]), lp(h[1][i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh);
       }
-      QuadIO::store<P::kStorePol>(lp(phc[0]), lp(psc[0]), lp(phc[1]), lp(psc[1]), rdrest, brest_s,
-                    unsigned(y) * rrow);
+      QuadIO::store<P::kStorePol>(lp(phc[0]), lp(psc[0]), lp(phc[1]), lp(psc[1]), rdrest,
+                                  brest_s, unsigned(y) * rrow);
       if constexpr (NS) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const unsigned bk = baux_s + unsigned(k) * P::kAux * EA;
           if constexpr (HAS_S)
-            QuadIO::store<P::kStorePol>(lp(oux[k]), lp(ouy[k]), lp(oSx[k]), lp(oSy[k]), raux, bk,
-                          unsigned(y) * arow);
+            QuadIO::store<P::kStorePol>(lp(oux[k]), lp(ouy[k]), lp(oSx[k]), lp(oSy[k]), raux,
+                                        bk, unsigned(y) * arow);
           else
             PairIO<A>::template store<P::kStorePol>(
                 lp(oux[k]), lp(ouy[k]), raux, bk, unsigned(y) * arow);
         }
+      }
+    } else {  // float16 deviations, scaled: four halves per (f, g) plane, two per h plane
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        u32x2 w;
+        w[0] = lane_pick<HL>(interior, halves(dc[0][i] * sc.f, qc[0][i] * sc.g));
+        w[1] = lane_pick<HL>(interior, halves(dc[1][i] * sc.f, qc[1][i] * sc.g));
+        __builtin_amdgcn_raw_buffer_store_b64(w, rdst, cs.p0, rcs + unsigned(i) * nxb,
+                                              P::kStorePol);
+      }
+      if constexpr (NS) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          __builtin_amdgcn_raw_buffer_store_b32(
+              lane_pick<HL>(interior, halves(h[0][i] * sc.h, h[1][i] * sc.h)), rdst, cs.h0,
+              rcs + hb + unsigned(i) * nxh, P::kStorePol);
+      }
+      if constexpr (P::HDEV && NS) {
+        // the two 5-float rest records (40 bytes) as 16 + 16 + 8 bytes
+        QuadIO::store<P::kStorePol>(lp(phc[0]), lp(psc[0]), lp(hn.pr[0]), lp(hn.jx[0]), rdrest,
+                                    brest_s, unsigned(y) * rrow);
+        QuadIO::store<P::kStorePol>(lp(hn.jy[0]), lp(phc[1]), lp(psc[1]), lp(hn.pr[1]), rdrest,
+                                    brest_s + 4 * EA, unsigned(y) * rrow);
+        PairIO<A>::template store<P::kStorePol>(lp(hn.jx[1]), lp(hn.jy[1]), rdrest,
+                                                brest_s + 8 * EA, unsigned(y) * rrow);
+        if constexpr (HAS_S)
+          QuadIO::store<P::kStorePol>(lp(oSx[0]), lp(oSy[0]), lp(oSx[1]), lp(oSy[1]), raux,
+                                      baux_s + P::kAuxS * EA, unsigned(y) * arow);
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          PairIO<A>::template store<P::kStorePol>(lp(phc[k]), lp(psc[k]), rdrest,
+                                                  brest_s + unsigned(k) * P::kRest * EA,
+                                                  unsigned(y) * rrow);
       }
     }
 
@@ -1438,8 +1557,8 @@ lbm_init_kernel(const SiteArgs<P> a, const Phys<double> p) {
   const long long pl = a.plane;
   const double *phi0 = a.scratch, *psi0 = a.scratch + pl;
   const double *ux0 = a.scratch + 2 * pl, *uy0 = a.scratch + 3 * pl;
-  const Nine<double> v = gather9<double>([&](int yy, int xx) { return phi0[(long long)yy * nx + xx]; },
-                                         x, y, nx, a.ny, a.walls);
+  const Nine<double> v = gather9<double>(
+      [&](int yy, int xx) { return phi0[(long long)yy * nx + xx]; }, x, y, nx, a.ny, a.walls);
   double gx, gy;
   grad9(v, gx, gy);
   const double phi = phi0[k], psi = psi0[k], ux = ux0[k], uy = uy0[k];
@@ -1924,11 +2043,11 @@ SiteArgs<P> site_args(lbm_handle *h) {
   return a;
 }
 
-// Columns per lane of the step kernel: two for float32 storage when nx is
-// even (each lane's pair of columns then never straddles the periodic
-// seam), else one.
+// Columns per lane of the step kernel: two for float32 and float16 storage
+// when nx is even (each lane's pair of columns then never straddles the
+// periodic seam), else one.
 int sites_per_lane(const lbm_params &p) {
-  return p.precision == LBM_FP32 && p.nx % 2 == 0 ? 2 : 1;
+  return p.precision != LBM_FP64 && p.nx % 2 == 0 ? 2 : 1;
 }
 int strips_of(const lbm_params &p) {
   const int cols = sites_per_lane(p) == 2 ? Strip<2>::kCols : Strip<1>::kCols;
@@ -1942,7 +2061,7 @@ int default_rows(const lbm_params &p) {
   // cache.  Measured on 2048x2048: 2 rows for float32 with two columns per
   // lane, 3 with one, 4 for float16 and float64 storage.
   const long long target = p.precision == LBM_FP32 ? 24576 : 16384;
-  const long long lo = sites_per_lane(p) == 2 ? 2 : 3;
+  const long long lo = p.precision != LBM_FP32 ? 4 : (sites_per_lane(p) == 2 ? 2 : 3);
   long long rows = strips * p.ny / target;
   if (rows < lo) rows = lo;
   if (rows > 64) rows = 64;
@@ -1989,7 +2108,9 @@ hipError_t run_step(lbm_handle *h) {
     case LBM_FP32:
       return sites_per_lane(h->p) == 2 ? launch_step_prec<F32, 2>(h)
                                        : launch_step_prec<F32, 1>(h);
-    default: return launch_step_prec<F16, 1>(h);
+    default:
+      return sites_per_lane(h->p) == 2 ? launch_step_prec<F16, 2>(h)
+                                       : launch_step_prec<F16, 1>(h);
   }
 }
 
@@ -2318,11 +2439,12 @@ namespace {
 
 
 // Kernel variants: storage precision x prescribed velocity x (r != 1) x
-// (rho_A != rho_B); float32 storage with two columns per lane is a fourth
-// group after the three precisions.
-constexpr int kClasses = 32;
+// (rho_A != rho_B); float32 and float16 storage with two columns per lane
+// are a fourth and a fifth group after the three precisions.
+constexpr int kClasses = 40;
 int class_of(const lbm_handle *h) {
-  const int group = sites_per_lane(h->p) == 2 ? 3 : int(h->p.precision);
+  int group = int(h->p.precision);
+  if (sites_per_lane(h->p) == 2) group = h->p.precision == LBM_FP32 ? 3 : 4;
   return group * 8 + (h->ns ? 0 : 4) + (h->genr ? 2 : 0) + (h->has_s ? 1 : 0);
 }
 
@@ -2388,7 +2510,10 @@ void launch_batch_prec(int c, int blocks, hipStream_t st, const void *desc,
 }
 
 // Storage precision of a kernel variant class (its descriptor array).
-int class_precision(int c) { return c / 8 == 3 ? int(LBM_FP32) : c / 8; }
+int class_precision(int c) {
+  const int g = c / 8;
+  return g == 3 ? int(LBM_FP32) : (g == 4 ? int(LBM_FP16DEV) : g);
+}
 
 void launch_batch_class(int c, int blocks, hipStream_t st, const void *desc,
                         const TileRef *tiles, const int *count, int k) {
@@ -2396,7 +2521,8 @@ void launch_batch_class(int c, int blocks, hipStream_t st, const void *desc,
     case LBM_FP64: launch_batch_prec<F64, 1>(c, blocks, st, desc, tiles, count, k); break;
     case LBM_FP32: launch_batch_prec<F32, 1>(c, blocks, st, desc, tiles, count, k); break;
     case LBM_FP16DEV: launch_batch_prec<F16, 1>(c, blocks, st, desc, tiles, count, k); break;
-    default: launch_batch_prec<F32, 2>(c, blocks, st, desc, tiles, count, k); break;
+    case 3: launch_batch_prec<F32, 2>(c, blocks, st, desc, tiles, count, k); break;
+    default: launch_batch_prec<F16, 2>(c, blocks, st, desc, tiles, count, k); break;
   }
 }
 

@@ -137,26 +137,31 @@ def test_ragged_and_tiny_grids(nx, ny):
     check(got, want, 1e-12, f"grid {nx}x{ny}")
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16dev"])
 @pytest.mark.parametrize("nx,ny,walls", [(4, 5, True), (6, 3, False), (122, 7, True),
                                          (124, 9, False), (126, 5, True), (250, 6, False),
                                          (248, 4, True)])
-def test_two_column_lanes_fp32(nx, ny, walls):
-    """float32 storage with an even nx runs two columns per lane (124
-    interior columns per wavefront): widths at and around one and two
+def test_two_column_lanes(nx, ny, walls, precision):
+    """float32 and float16 storage with an even nx run two columns per lane
+    (124 interior columns per wavefront): widths at and around one and two
     strips, narrower than a wavefront, and the seam of the periodic wrap
     falling inside a lane pair of the halo."""
     pr = W.random_small(200 + nx, nx=nx, ny=ny, walls=walls, steps=20)
-    _, got = run_gpu(pr, "fp32", pr.steps)
+    _, got = run_gpu(pr, precision, pr.steps)
     _, want = run_oracle(pr, pr.steps)
-    check(got, want, TOL["fp32"], f"fp32 pairs {nx}x{ny} walls={walls}", FIELDS + ("P",))
+    check(got, want, TOL[precision], f"{precision} pairs {nx}x{ny} walls={walls}",
+          FIELDS + ("P",))
 
 
-def test_tile_height_does_not_change_results_fp32_pairs():
-    """Two columns per lane: every tile height gives the same bits."""
-    pr = W.random_small(5, nx=250, ny=40, walls=True, steps=15)
+@pytest.mark.parametrize("precision,nx", [("fp32", 250), ("fp16dev", 250), ("fp32", 251),
+                                         ("fp16dev", 251)])
+def test_tile_height_does_not_change_results_reduced(precision, nx):
+    """float32 and float16 storage, two columns per lane (even nx) and one
+    (odd nx): every tile height gives the same bits."""
+    pr = W.random_small(5, nx=nx, ny=40, walls=True, steps=15)
     outs = []
     for rows in (1, 3, 7, 40):
-        _, got = run_gpu(pr, "fp32", pr.steps, rows=rows)
+        _, got = run_gpu(pr, precision, pr.steps, rows=rows)
         outs.append(got)
     for o in outs[1:]:
         for k in ("phi", "psi", "ux", "uy", "P"):
