@@ -1,35 +1,39 @@
 // HIP kernels and C ABI of the coupled three-field lattice Boltzmann library
 // (phase field f, surfactant g, flow h; arXiv:2408.15654), for gfx950.
 //
-// State on the device, row-interleaved structure of arrays: for each row y
-// the rows of all planes of a group follow each other (element (plane q,
-// row y, column x) of a group of NP planes is at (y*NP + q)*nx + x), so one
-// lattice row of every population lies in one contiguous block.  Two
+// State on the device (one caller-owned workspace per simulation).  Two
 // copies (ping-pong) of:
-//   populations  planes 0-8: deviations d_i = f_i - w_i phi of the
-//                post-collision phase-field populations from the rest
-//                equilibrium of their own site; 9-17: the same for g with
-//                psi; 18-25: h_1..h_8 (h_0 is never read: column 0 of M is
-//                e_0 and rows 1-8 of M^-1 start with 0);
-//   rest         planes phi, psi of the same (previous) time level.
-// plus, updated in place (each site reads and writes only its own entries):
-//   aux          planes ux, uy, Sx, Sy of the previous time level (the
-//                first-order time differences need them; phi, psi come from
-//                the rest planes);
+//   populations  row-interleaved: lattice row y holds the FG block (for
+//                i = 0..8, nx pairs (f_i, g_i), so the two populations that
+//                stream from the same source site arrive in one access) and
+//                then the H block (h_1..h_8, nx each; h_0 is never read:
+//                column 0 of M is e_0 and rows 1-8 of M^-1 start with 0).
+//                f_i and g_i are stored as deviations f_i - w_i phi and
+//                g_i - w_i psi from the rest values of the writing site;
+//   rest         one record per site, (phi, psi) of the same time level:
+//                the bases of those deviations;
+// plus, updated in place (each site reads and writes only its own entry):
+//   aux          one record per site, (ux, uy, Sx, Sy) of the previous time
+//                level (the first-order time differences need them); with a
+//                prescribed velocity, u itself;
 //   scratch      float64 planes (plane-major) for host transfers and
 //                read-back.
-// Storage type: float64, float32, or float16 with per-field power-of-two
-// scales (deviations and h are small numbers; phi, psi stay float32).
+// Storage: float64, float32, or float16 deviations with per-field
+// power-of-two scales; with float16 storage h is also stored as deviations,
+// from 3 w_k (P + c_k . rho u) of the writing site, the rest record carries
+// (phi, psi, P, rho ux, rho uy) in float32 and aux only (Sx, Sy).
 //
 // One time step is ONE launch of lbm_step_kernel.  Each wavefront owns a
-// strip of 60 columns (plus two halo columns on each side) and walks down a
-// tile of rows.  For each row it pulls the f and g
-// deviations of the NEXT row, rebuilds that row's phi, psi (and sigma(psi))
-// from them and the rest values of their source sites, keeps a three-row
-// window of phi, psi, sigma in registers and takes x-neighbours from
-// adjacent lanes with cross-lane moves, so the 9-point stencils need no LDS
-// and no barrier.  The h populations and the previous level are read for
-// the current row only, and every population is written once.
+// strip of columns, 60 with one column per lane or 124 with two (float32
+// and float16 storage, even nx), plus two halo columns on each side, and
+// walks down a tile of rows.  For each row it pulls the f and g deviations
+// of the NEXT row, rebuilds that row's phi, psi (and sigma(psi)) from them
+// and the rest values of their source sites, keeps a three-row window of
+// phi, psi, sigma in registers and takes x-neighbours from adjacent lanes
+// with cross-lane moves, so the 9-point stencils need no LDS and no
+// barrier.  The h populations and the previous level are read for the
+// current row only, and every population is written once.  Workgroups walk
+// the tiles in one contiguous band per XCD.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -540,20 +544,6 @@ __device__ __forceinline__ void shift_k(const R *v, int sh, R *out) {
   for (int k = 0; k < K; ++k) out[k] = sh > 0 ? l[k] : (sh < 0 ? r[k] : v[k]);
 }
 
-template <class R>
-__device__ __forceinline__ Nine<R> window(R m, R c, R n) {
-  Nine<R> v;
-  v.m = m;
-  v.c = c;
-  v.n = n;
-  v.mL = from_left(m);
-  v.mR = from_right(m);
-  v.cL = from_left(c);
-  v.cR = from_right(c);
-  v.nL = from_left(n);
-  v.nR = from_right(n);
-  return v;
-}
 
 // Pairs through one buffer access.  Vector elements are copied to scalars
 // before any reinterpretation: a bit cast applied directly to an element
@@ -839,8 +829,7 @@ struct Pull2 {
   static_assert((!P::SCALED && sizeof(S) == 4) || (P::SCALED && sizeof(S) == 2),
                 "float32 or scaled float16 storage");
   static __device__ __forceinline__ void fg(rsrc_t rs, unsigned nxb, const RowOff &r,
-                                            unsigned col, const Scales<P> &sc, R (*f)[9],
-                                            R (*g)[9]) {
+                                            unsigned col, R (*f)[9], R (*g)[9]) {
     auto quad = [&](unsigned row, int i) {
       if constexpr (sizeof(S) == 4) {
         QuadIO::load(rs, col, row, f[0][i], g[0][i], f[1][i], g[1][i]);
@@ -919,7 +908,7 @@ struct Pull2 {
     }
   }
   static __device__ __forceinline__ void h(rsrc_t rs, unsigned hb, unsigned nxh,
-                                           const RowOff &r, unsigned col, R inv, R (*out)[8]) {
+                                           const RowOff &r, unsigned col, R (*out)[8]) {
     auto two = [&](unsigned off, int k) {
       if constexpr (sizeof(S) == 4) {
         PairIO<float>::load(rs, col, off + hb, out[0][k], out[1][k]);
@@ -1038,7 +1027,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     if constexpr (K == 1)
       Pull<P>::fg(rsrc, nxb, o, co, sc, d[0], q[0]);
     else
-      Pull2<P>::fg(rsrc, nxb, o, co.p0, sc, d, q);
+      Pull2<P>::fg(rsrc, nxb, o, co.p0, d, q);
   };
   // loads of row y that the rebuild of row y+1 does not need
   auto load_row = [&](int y, R (*h)[8], R *uxp, R *uyp, R *Sxp, R *Syp) {
@@ -1047,7 +1036,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       if constexpr (K == 1)
         Pull<P>::h(rsrc, hb, nxh, o, co, sc.hi, h[0]);
       else
-        Pull2<P>::h(rsrc, hb, nxh, o, co.h0, sc.hi, h);
+        Pull2<P>::h(rsrc, hb, nxh, o, co.h0, h);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -2436,7 +2425,6 @@ const char *lbm_step_kernel_name(const lbm_handle *h) {
 // ------------------------------------------------------------ batch runtime
 
 namespace {
-
 
 // Kernel variants: storage precision x prescribed velocity x (r != 1) x
 // (rho_A != rho_B); float32 and float16 storage with two columns per lane
