@@ -10,6 +10,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -20,23 +21,36 @@ HEADERS = [os.path.join(CSRC, "lbm_device.h"), os.path.join(CSRC, "arena.h"),
            os.path.join(ROOT, "include", "lbm.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# -ffp-contract=off: no multiply-add is fused unless written as one, so a
-# site's arithmetic gives the same bits in every copy of the step kernel's
-# row code (prologue, loop, last row) and the results do not depend on the
-# tile height.  Float16 storage rounds stochastically from all 32 bits of
-# each value, where a one-ulp difference would change the stored value.
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-         "-ffp-contract=off",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+# lbm.hip is compiled twice.  The second pass (LBM_F16_PART) holds only the
+# float16 step kernels, built with -ffp-contract=off: no multiply-add is
+# fused unless written as one, so a site's arithmetic gives the same bits in
+# every copy of the row code and float16 storage (which rounds
+# stochastically from all 32 bits of each value) stays independent of the
+# tile height.
+PASSES = (("main", []), ("f16", ["-DLBM_F16_PART", "-ffp-contract=off"]))
 
 
 def build(verbose: bool = False) -> str:
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    with tempfile.TemporaryDirectory() as d:
+        objs, procs = [], []
+        for tag, extra in PASSES:
+            obj = os.path.join(d, f"lbm_{tag}.o")
+            cmd = [HIPCC, *FLAGS, *extra, "-c", "-o", obj, *SOURCES]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((subprocess.Popen(cmd), cmd))
+            objs.append(obj)
+        for proc, cmd in procs:
+            if proc.wait() != 0:
+                raise subprocess.CalledProcessError(proc.returncode, cmd)
+        tmp = LIB + f".tmp{os.getpid()}"
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
 

@@ -2069,20 +2069,8 @@ struct lbm_handle {
   std::string err;
 };
 
+// Step launches: compiled in both passes of this file (see lbm_f16_part).
 namespace {
-
-lbm_status fail(lbm_handle *h, lbm_status s, const std::string &msg) {
-  if (h)
-    h->err = msg;
-  else
-    g_create_error = msg;
-  return s;
-}
-
-lbm_status hip_check(lbm_handle *h, hipError_t e, const char *what) {
-  if (e == hipSuccess) return LBM_OK;
-  return fail(h, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
 
 void *pops(lbm_handle *h, int which) { return h->ws + h->L.off_pop[which]; }
 void *rest(lbm_handle *h, int which) { return h->ws + h->L.off_rest[which]; }
@@ -2090,24 +2078,6 @@ void *auxp(lbm_handle *h) { return h->ws + h->L.off_aux; }
 double *scratch(lbm_handle *h) { return reinterpret_cast<double *>(h->ws + h->L.off_scratch); }
 double *partials(lbm_handle *h) { return reinterpret_cast<double *>(h->ws + h->L.off_partial); }
 int *flagp(lbm_handle *h) { return reinterpret_cast<int *>(h->ws + h->L.off_flag); }
-
-template <class P>
-SiteArgs<P> site_args(lbm_handle *h) {
-  SiteArgs<P> a;
-  a.src = static_cast<const typename P::S *>(pops(h, h->cur));
-  a.src_rest = static_cast<const typename P::A *>(rest(h, h->cur));
-  a.dst = static_cast<typename P::S *>(pops(h, h->cur));
-  a.dst_rest = static_cast<typename P::A *>(rest(h, h->cur));
-  a.aux = static_cast<typename P::A *>(auxp(h));
-  a.scratch = scratch(h);
-  a.sc = make_scales<P>(h->p);
-  a.plane = h->L.plane;
-  a.nx = h->p.nx;
-  a.ny = h->p.ny;
-  a.walls = h->p.walls_y;
-  a.ns = h->ns ? 1 : 0;
-  return a;
-}
 
 // Columns per lane of the step kernel: two for float32 and float16 storage
 // when nx is even (each lane's pair of columns then never straddles the
@@ -2118,20 +2088,6 @@ int sites_per_lane(const lbm_params &p) {
 int strips_of(const lbm_params &p) {
   const int cols = sites_per_lane(p) == 2 ? Strip<2>::kCols : Strip<1>::kCols;
   return (p.nx + cols - 1) / cols;
-}
-
-int default_rows(const lbm_params &p) {
-  const long long strips = strips_of(p);
-  // Many short tiles keep the wavefronts' start-up and drain phases
-  // staggered; the two extra halo rows per tile are served mostly from
-  // cache.  Measured on 2048x2048: 2 rows for float32 with two columns per
-  // lane, 3 with one, 4 for float16 and float64 storage.
-  const long long target = p.precision == LBM_FP32 ? 24576 : 16384;
-  const long long lo = p.precision != LBM_FP32 ? 4 : (sites_per_lane(p) == 2 ? 2 : 3);
-  long long rows = strips * p.ny / target;
-  if (rows < lo) rows = lo;
-  if (rows > 64) rows = 64;
-  return int(rows);
 }
 
 template <class P, int K, bool GENR, bool HAS_S, bool NS>
@@ -2168,15 +2124,114 @@ hipError_t launch_step_prec(lbm_handle *h) {
                   : launch_step<P, K, false, false, true>(h);
 }
 
+template <class P, int K, bool GENR, bool HAS_S, bool NS>
+void launch_batch(int blocks, hipStream_t st, const void *desc, const TileRef *tiles,
+                  const int *count, int k) {
+  hipLaunchKernelGGL((lbm_batch_step_kernel<P, K, GENR, HAS_S, NS>), dim3(blocks),
+                     dim3(kWave * kWavesPerBlock), 0, st,
+                     static_cast<const BatchInst<P> *>(desc), tiles, count, k);
+}
+
+template <class P, int K>
+void launch_batch_prec(int c, int blocks, hipStream_t st, const void *desc,
+                       const TileRef *tiles, const int *count, int k) {
+  switch (c & 7) {
+    case 0: launch_batch<P, K, false, false, true>(blocks, st, desc, tiles, count, k); break;
+    case 1: launch_batch<P, K, false, true, true>(blocks, st, desc, tiles, count, k); break;
+    case 2: launch_batch<P, K, true, false, true>(blocks, st, desc, tiles, count, k); break;
+    case 3: launch_batch<P, K, true, true, true>(blocks, st, desc, tiles, count, k); break;
+    case 4: launch_batch<P, K, false, false, false>(blocks, st, desc, tiles, count, k); break;
+    default: launch_batch<P, K, true, false, false>(blocks, st, desc, tiles, count, k); break;
+  }
+}
+
+}  // namespace
+
+// The float16 step kernels are compiled in a second pass of this file
+// (LBM_F16_PART) without FP contraction.  Float16 storage rounds
+// stochastically from all 32 bits of each value, so every copy of the row
+// code must give the same bits for the results not to depend on the tile
+// height; the float32 and float64 kernels keep fused multiply-adds (1-2%
+// faster) and are tile-height independent with them.
+namespace lbm_f16_part {
+hipError_t step(lbm_handle *h);
+void batch(int c, int blocks, hipStream_t st, const void *desc, const void *tiles,
+           const int *count, int k);
+}  // namespace lbm_f16_part
+
+#ifdef LBM_F16_PART
+namespace lbm_f16_part {
+hipError_t step(lbm_handle *h) {
+  return sites_per_lane(h->p) == 2 ? launch_step_prec<F16, 2>(h) : launch_step_prec<F16, 1>(h);
+}
+void batch(int c, int blocks, hipStream_t st, const void *desc, const void *tiles,
+           const int *count, int k) {
+  const TileRef *t = static_cast<const TileRef *>(tiles);
+  if (c / 8 == int(LBM_FP16DEV))
+    launch_batch_prec<F16, 1>(c, blocks, st, desc, t, count, k);
+  else
+    launch_batch_prec<F16, 2>(c, blocks, st, desc, t, count, k);
+}
+}  // namespace lbm_f16_part
+#else
+
+namespace {
+
+lbm_status fail(lbm_handle *h, lbm_status s, const std::string &msg) {
+  if (h)
+    h->err = msg;
+  else
+    g_create_error = msg;
+  return s;
+}
+
+lbm_status hip_check(lbm_handle *h, hipError_t e, const char *what) {
+  if (e == hipSuccess) return LBM_OK;
+  return fail(h, LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+
+template <class P>
+SiteArgs<P> site_args(lbm_handle *h) {
+  SiteArgs<P> a;
+  a.src = static_cast<const typename P::S *>(pops(h, h->cur));
+  a.src_rest = static_cast<const typename P::A *>(rest(h, h->cur));
+  a.dst = static_cast<typename P::S *>(pops(h, h->cur));
+  a.dst_rest = static_cast<typename P::A *>(rest(h, h->cur));
+  a.aux = static_cast<typename P::A *>(auxp(h));
+  a.scratch = scratch(h);
+  a.sc = make_scales<P>(h->p);
+  a.plane = h->L.plane;
+  a.nx = h->p.nx;
+  a.ny = h->p.ny;
+  a.walls = h->p.walls_y;
+  a.ns = h->ns ? 1 : 0;
+  return a;
+}
+
+
+int default_rows(const lbm_params &p) {
+  const long long strips = strips_of(p);
+  // Many short tiles keep the wavefronts' start-up and drain phases
+  // staggered; the two extra halo rows per tile are served mostly from
+  // cache.  Measured on 2048x2048: 2 rows for float32 with two columns per
+  // lane, 3 with one, 4 for float16 and float64 storage.
+  const long long target = p.precision == LBM_FP32 ? 24576 : 16384;
+  const long long lo = p.precision != LBM_FP32 ? 4 : (sites_per_lane(p) == 2 ? 2 : 3);
+  long long rows = strips * p.ny / target;
+  if (rows < lo) rows = lo;
+  if (rows > 64) rows = 64;
+  return int(rows);
+}
+
+
 hipError_t run_step(lbm_handle *h) {
   switch (h->p.precision) {
     case LBM_FP64: return launch_step_prec<F64, 1>(h);
     case LBM_FP32:
       return sites_per_lane(h->p) == 2 ? launch_step_prec<F32, 2>(h)
                                        : launch_step_prec<F32, 1>(h);
-    default:
-      return sites_per_lane(h->p) == 2 ? launch_step_prec<F16, 2>(h)
-                                       : launch_step_prec<F16, 1>(h);
+    default: return lbm_f16_part::step(h);
   }
 }
 
@@ -2553,26 +2608,6 @@ void fill_desc(void *dst, const lbm_handle *h, int steps) {
   std::memcpy(dst, &d, sizeof d);
 }
 
-template <class P, int K, bool GENR, bool HAS_S, bool NS>
-void launch_batch(int blocks, hipStream_t st, const void *desc, const TileRef *tiles,
-                  const int *count, int k) {
-  hipLaunchKernelGGL((lbm_batch_step_kernel<P, K, GENR, HAS_S, NS>), dim3(blocks),
-                     dim3(kWave * kWavesPerBlock), 0, st,
-                     static_cast<const BatchInst<P> *>(desc), tiles, count, k);
-}
-
-template <class P, int K>
-void launch_batch_prec(int c, int blocks, hipStream_t st, const void *desc,
-                       const TileRef *tiles, const int *count, int k) {
-  switch (c & 7) {
-    case 0: launch_batch<P, K, false, false, true>(blocks, st, desc, tiles, count, k); break;
-    case 1: launch_batch<P, K, false, true, true>(blocks, st, desc, tiles, count, k); break;
-    case 2: launch_batch<P, K, true, false, true>(blocks, st, desc, tiles, count, k); break;
-    case 3: launch_batch<P, K, true, true, true>(blocks, st, desc, tiles, count, k); break;
-    case 4: launch_batch<P, K, false, false, false>(blocks, st, desc, tiles, count, k); break;
-    default: launch_batch<P, K, true, false, false>(blocks, st, desc, tiles, count, k); break;
-  }
-}
 
 // Storage precision of a kernel variant class (its descriptor array).
 int class_precision(int c) {
@@ -2585,9 +2620,8 @@ void launch_batch_class(int c, int blocks, hipStream_t st, const void *desc,
   switch (c / 8) {
     case LBM_FP64: launch_batch_prec<F64, 1>(c, blocks, st, desc, tiles, count, k); break;
     case LBM_FP32: launch_batch_prec<F32, 1>(c, blocks, st, desc, tiles, count, k); break;
-    case LBM_FP16DEV: launch_batch_prec<F16, 1>(c, blocks, st, desc, tiles, count, k); break;
     case 3: launch_batch_prec<F32, 2>(c, blocks, st, desc, tiles, count, k); break;
-    default: launch_batch_prec<F16, 2>(c, blocks, st, desc, tiles, count, k); break;
+    default: lbm_f16_part::batch(c, blocks, st, desc, tiles, count, k); break;
   }
 }
 
@@ -3081,3 +3115,5 @@ const char *lbm_batch_last_error(const lbm_batch *b) {
 }
 
 }  // extern "C"
+
+#endif  // LBM_F16_PART
