@@ -57,7 +57,11 @@ typedef enum {
  * float32 arithmetic and float32 phi, psi: f_i - w_i phi and g_i - w_i psi
  * (the rest equilibria of Eqs. (22), (26)), and h_i - 3 w_i (P + c_i . rho u)
  * (the part of Eq. (30) linear in P and rho u), each relative to the stored
- * values of the site that wrote it. */
+ * values of the site that wrote it.  The float16 values are rounded
+ * stochastically (reproducibly: the random bits are a hash of the values
+ * and the site), and a site's rounding errors of f_1..f_8, g_1..g_8 are
+ * carried into f_0, g_0, so the sums of phi and psi change by one rounding
+ * per site and step. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16DEV = 2 } lbm_precision;
 
 /* Equation of state sigma(psi): linear Eq. (20) or Langmuir Eq. (19). */

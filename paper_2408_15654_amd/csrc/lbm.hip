@@ -133,36 +133,6 @@ struct Scales {
   typename P::R fi, gi, hi;  // multiply after loading
 };
 
-// Element at a 32-bit byte offset from a (wave-uniform) base pointer: the
-// address is then an SGPR base plus one VGPR offset.
-template <class T>
-__device__ __forceinline__ const T &at(const T *base, unsigned byte_off) {
-  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
-}
-template <class T>
-__device__ __forceinline__ T &at(T *base, unsigned byte_off) {
-  return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
-}
-
-template <class P>
-__device__ __forceinline__ typename P::R ldb(const typename P::S *p, unsigned byte_off,
-                                             typename P::R inv) {
-  using R = typename P::R;
-  if constexpr (P::SCALED)
-    return R(at(p, byte_off)) * inv;
-  else
-    return R(at(p, byte_off));
-}
-template <class P>
-__device__ __forceinline__ void stb(typename P::S *p, unsigned byte_off, typename P::R v,
-                                    typename P::R scale) {
-  using S = typename P::S;
-  if constexpr (P::SCALED)
-    at(p, byte_off) = S(v * scale);
-  else
-    at(p, byte_off) = S(v);
-}
-
 // Buffer-resource memory access for the step kernel: the address is a
 // wave-uniform resource (SGPRs) plus a uniform byte offset (SGPR) plus one
 // per-lane 32-bit byte offset (VGPR), so no per-lane 64-bit address math.
@@ -220,14 +190,10 @@ struct BufIO<_Float16> {
   static __device__ __forceinline__ _Float16 load(rsrc_t r, unsigned v, unsigned s) {
     return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
   }
-  template <int POL>
-  static __device__ __forceinline__ void store(_Float16 x, rsrc_t r, unsigned v, unsigned s) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, POL);
-  }
 };
 
-// Population load / store through a buffer resource, with the float16
-// scale where the storage is scaled.
+// Population load through a buffer resource, with the float16 scale where
+// the storage is scaled; store of an unscaled (float32/float64) one.
 template <class P>
 __device__ __forceinline__ typename P::R bld(rsrc_t r, unsigned v, unsigned s,
                                              typename P::R inv) {
@@ -239,13 +205,9 @@ __device__ __forceinline__ typename P::R bld(rsrc_t r, unsigned v, unsigned s,
     return R(BufIO<typename P::S>::load(r, v, s));
 }
 template <class P>
-__device__ __forceinline__ void bst(typename P::R x, rsrc_t r, unsigned v, unsigned s,
-                                    typename P::R scale) {
-  using S = typename P::S;
-  if constexpr (P::SCALED)
-    BufIO<S>::template store<P::kStorePol>(S(x * scale), r, v, s);
-  else
-    BufIO<S>::template store<P::kStorePol>(S(x), r, v, s);
+__device__ __forceinline__ void bst(typename P::R x, rsrc_t r, unsigned v, unsigned s) {
+  static_assert(!P::SCALED, "float16 populations are stored packed (halves_sr)");
+  BufIO<typename P::S>::template store<P::kStorePol>(typename P::S(x), r, v, s);
 }
 
 template <class P>
@@ -603,19 +565,9 @@ struct PairIO<_Float16> {
     a = __builtin_bit_cast(_Float16, lo);
     b = __builtin_bit_cast(_Float16, hi);
   }
-  template <int POL>
-  static __device__ __forceinline__ void store(_Float16 a, _Float16 b, rsrc_t r, unsigned v,
-                                               unsigned s) {
-    const unsigned short lo = __builtin_bit_cast(unsigned short, a),
-                         hi = __builtin_bit_cast(unsigned short, b);
-    const unsigned w = unsigned(lo) | (unsigned(hi) << 16);
-    __builtin_amdgcn_raw_buffer_store_b32(w, r, v, s, POL);
-  }
 };
 
-// Three floats: one 96-bit load; stored as 64 + 32 bits, so the store
-// needs no guard (the float16 path then keeps its stores unfenced and the
-// scheduler free to sink conversions past them).
+// Three floats through one 96-bit load.
 typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 struct TripleIO {
   static __device__ __forceinline__ void load(rsrc_t r, unsigned v, unsigned s, float &a,
@@ -625,15 +577,6 @@ struct TripleIO {
     a = __uint_as_float(w0);
     b = __uint_as_float(w1);
     c = __uint_as_float(w2);
-  }
-  template <int POL>
-  static __device__ __forceinline__ void store(float a, float b, float c, rsrc_t r, unsigned v,
-                                               unsigned s) {
-    u32x2 w;
-    w[0] = __float_as_uint(a);
-    w[1] = __float_as_uint(b);
-    __builtin_amdgcn_raw_buffer_store_b64(w, r, v, s, POL);
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(c), r, v + 8, s, POL);
   }
 };
 
@@ -1343,7 +1286,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       } else if constexpr (NS) {
 #pragma unroll
         for (int i = 0; i < 8; ++i)
-          bst<P>(lp(h[0][i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh, sc.h);
+          bst<P>(lp(h[0][i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh);
       }
       if constexpr (P::HDEV && NS) {  // (phi, psi, P, rho ux) and rho uy
         QuadIO::store<P::kStorePol>(lp(phc[0]), lp(psc[0]), lp(hn.pr[0]), lp(hn.jx[0]), rdrest,
