@@ -222,8 +222,10 @@ const char *lbm_step_kernel_name(const lbm_handle *h);
  * use.  Simulations may differ in size, parameters and precision.  Every
  * lbm_batch_step advances all admitted simulations that still have steps
  * left, in launches of one persistent kernel per kernel variant present
- * (storage precision, r == 1 or not, equal densities or not); a chunk of
- * those launches is captured once as a HIP graph and replayed.  The
+ * (storage precision; one or two columns per lane, two for float32 and
+ * float16 storage with even nx; Navier-Stokes or prescribed flow; r == 1
+ * or not; equal densities or not); a chunk of those launches is captured
+ * once as a HIP graph and replayed.  The
  * arithmetic of each simulation is exactly that of lbm_step on its own
  * (bitwise), whatever the batch holds and whatever the schedule.
  *
