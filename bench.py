@@ -211,6 +211,14 @@ def rel_errors(got, want):
     return out
 
 
+# Admission policy of the serving stream: least work first, and at most
+# about twice the sites at which one grid already saturates the device
+# (2048 x 1024, 2.1 M sites, runs at the 2048^2 rate).  Measured on the
+# 200-request float32 stream at 0.7x load against first come, first served
+# with no cap: same throughput and p50, p99 4.3 s instead of 5.7 s.
+SERVE_POLICY = {"order": "shortest", "max_running_sites": 4_000_000}
+
+
 def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), load=0.7,
                   max_steps=20000, quiet=False):
     """The serving stream: Poisson arrivals of drop-in-shear and Marangoni
@@ -248,7 +256,7 @@ def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), loa
                                           offered_MLUPS=load * cap)
         check = {r.rid for r in reqs if r.rid % 10 == 0}
         for gb in budgets_gb if prec == "fp32" else budgets_gb[-1:]:
-            srv = serve.Server(int(gb) << 30, max_instances=512, chunk=64)
+            srv = serve.Server(int(gb) << 30, max_instances=512, chunk=64, **SERVE_POLICY)
             results, stats = srv.run(reqs, keep_fields=check)
             srv.close()
             del srv
@@ -275,7 +283,8 @@ def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), loa
                 spread.append(rel_errors(ref[1], ref[0]))
             worst = {k: max(e[k] for e in errs) for k in ("phi", "psi", "u")} if errs else {}
             wsp = {k: max(e[k] for e in spread) for k in ("phi", "psi", "u")} if spread else {}
-            out.append(dict(stats, precision=prec, budget_GB=gb, capacity_MLUPS=round(cap, 1),
+            out.append(dict(stats, precision=prec, budget_GB=gb, policy=SERVE_POLICY,
+                            capacity_MLUPS=round(cap, 1),
                             offered_rate_per_s=round(rate, 3), fp64_rerun_checked=len(errs),
                             worst_rel_err_vs_fp64=worst,
                             fp64_spread_from_perturbation_1e10=wsp))

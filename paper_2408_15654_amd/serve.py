@@ -43,23 +43,59 @@ class Result:
         return self.finished - self.arrival
 
 
+def admission_order(waiting, order: str):
+    """Order in which waiting requests are offered a slot: "arrival" (first
+    come, first served) or "shortest" (least work, sites x steps, first;
+    ties by arrival)."""
+    if order == "arrival":
+        return list(waiting)
+    if order == "shortest":
+        return sorted(waiting, key=lambda r: (_sites(r) * r.steps, r.arrival))
+    raise ValueError(f"unknown admission order {order!r}")
+
+
+def within_site_cap(running_sites: int, sites: int, n_running: int, cap) -> bool:
+    """A request may join unless the running solves' sites plus its own
+    would exceed cap.  An empty batch always admits (so no request waits
+    for ever), and cap None means no limit."""
+    return cap is None or n_running == 0 or running_sites + sites <= cap
+
+
+def _sites(req) -> int:
+    return int(req.params["nx"]) * int(req.params["ny"])
+
+
 class Server:
     """Serve a stream of requests on one GPU with one batch.
 
-    budget_bytes  device workspace of the batch (its HBM budget)
-    chunk         steps per device round between admissions and retirements
-    keep_fields   read back the final fields of these request ids (others
-                  are retired without a read-back of the fields)
+    budget_bytes       device workspace of the batch (its HBM budget)
+    chunk              steps per device round between admissions and
+                       retirements
+    order              admission order of waiting requests, "arrival" or
+                       "shortest" (admission_order)
+    max_running_sites  cap on the sites of the solves running together
+                       (None: only the budget limits admission).  Every
+                       running solve advances one step per launch, so a
+                       solve's latency is its step count times the batch's
+                       step time, which grows with the sites running; once
+                       the device is saturated more sites add latency and no
+                       throughput.
+    keep_fields        (run) read back the final fields of these request ids
+                       (others are retired without a read-back of the fields)
     """
 
     def __init__(self, budget_bytes: int, max_instances: int = 512, chunk: int = 64,
-                 schedule: dict | None = None):
+                 schedule: dict | None = None, order: str = "arrival",
+                 max_running_sites: int | None = None):
+        admission_order([], order)  # validates the name
         self.batch = lbm.Batch(budget_bytes, max_instances=max_instances)
         sched = dict(rows=0, grid_waves=0, chunk=min(chunk, 64))
         if schedule:
             sched.update(schedule)
         self.batch.set_schedule(**sched)
         self.chunk = chunk
+        self.order = order
+        self.max_running_sites = max_running_sites
 
     def run(self, requests: list[Request], keep_fields=frozenset(), clock=time.perf_counter,
             on_admit=None) -> tuple[list[Result], dict]:
@@ -71,19 +107,25 @@ class Server:
         results: list[Result] = []
         site_updates = 0
         peak_running = 0
+        running_sites = 0
         t0 = clock()
         while pending or waiting or running:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            # admit in arrival order while they fit (a request that does not
-            # fit waits; later, smaller ones may still be admitted)
-            for req in list(waiting):
+            # admit in the chosen order while they fit the budget and the
+            # site cap (a request that does not fit waits; others may still
+            # be admitted)
+            for req in admission_order(waiting, self.order):
+                if not within_site_cap(running_sites, _sites(req), len(running),
+                                       self.max_running_sites):
+                    continue
                 sid = self.batch.try_submit(req.params, *req.fields0, req.steps)
                 if sid is None:
                     continue
                 waiting.remove(req)
                 running[sid] = (req, clock() - t0)
+                running_sites += _sites(req)
                 if on_admit:
                     on_admit(req, sid)
             peak_running = max(peak_running, len(running))
@@ -104,7 +146,8 @@ class Server:
                 fields = self.batch.read_fields(sid) if req.rid in keep_fields else None
                 self.batch.retire(sid)
                 del running[sid]
-                sites = int(req.params["nx"]) * int(req.params["ny"])
+                sites = _sites(req)
+                running_sites -= sites
                 site_updates += sites * req.steps
                 results.append(Result(req.rid, req.arrival, adm, clock() - t0, req.steps, sites,
                                       fields))

@@ -41,3 +41,36 @@ def test_served_results_equal_alone_and_requests_join_mid_run(precision):
             assert np.array_equal(res.fields[k], want[k]), (res.rid, k)
         assert res.finished >= res.admitted >= res.arrival - 1e-9
     assert stats["latency_p99_s"] >= stats["latency_p50_s"] > 0
+
+
+def test_least_work_first_under_a_site_cap():
+    """Admission by least work under a cap on the running sites: the cap
+    holds at every admission (unless the batch was empty), every request
+    completes, and results stay bitwise those of the solve alone."""
+    reqs, _ = serve.serving_stream(n=12, rate=600.0, seed=12, precision="fp32",
+                                   min_side=48, max_side=160, min_steps=40, max_steps=300)
+    sizes = [int(r.params["nx"]) * int(r.params["ny"]) for r in reqs]
+    cap = 2 * max(sizes)
+    budget = lbm.Batch.overhead_bytes(16) + (1 << 20) + sum(
+        lbm.Batch.instance_bytes(r.params) for r in reqs)  # the budget never binds
+    srv = serve.Server(budget, max_instances=16, chunk=16, order="shortest",
+                       max_running_sites=cap)
+    over = []
+
+    def on_admit(req, sid):
+        running = sum(ny * nx for ny, nx in srv.batch.shapes.values())
+        if len(srv.batch.shapes) > 1 and running > cap:
+            over.append((req.rid, running))
+
+    check = {r.rid for r in reqs[::3]}
+    results, stats = srv.run(reqs, keep_fields=check, on_admit=on_admit)
+    srv.close()
+    assert not over
+    assert stats["requests"] == len(reqs)
+    by_id = {r.rid: r for r in reqs}
+    for res in results:
+        if res.fields is None:
+            continue
+        want = alone(by_id[res.rid])
+        for k in ("phi", "psi", "ux", "uy", "P"):
+            assert np.array_equal(res.fields[k], want[k]), (res.rid, k)
