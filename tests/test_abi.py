@@ -70,6 +70,22 @@ def test_workspace_bytes_and_validation_without_device():
     assert st == lbm.LBM_EINVAL
 
 
+def test_largest_accepted_grids():
+    """Each copy of the 26 population planes is addressed with 32-bit byte
+    offsets: the largest square grid per storage precision is accepted and
+    one more row and column is refused."""
+    lib = lbm.load()
+    pr = workloads.c1_stationary_drop()
+    for prec, side, bytes_per_pop in (("fp64", 4544, 8), ("fp32", 6426, 4),
+                                      ("fp16dev", 9088, 2)):
+        assert 26 * side * side * bytes_per_pop <= 0xFFFFFFFF
+        assert 26 * (side + 1) ** 2 * bytes_per_pop > 0xFFFFFFFF
+        ok = lbm.to_c_params(dict(pr.params, nx=side, ny=side, precision=prec))
+        assert lib.lbm_workspace_bytes(ctypes.byref(ok)) > 26 * side * side * bytes_per_pop
+        big = lbm.to_c_params(dict(pr.params, nx=side + 1, ny=side + 1, precision=prec))
+        assert lib.lbm_workspace_bytes(ctypes.byref(big)) == 0, prec
+
+
 def test_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(ImportError):
         lbm._lib_backup = lbm._lib

@@ -179,6 +179,41 @@ def test_many_drops_full_size(precision):
     check(got, want, TOL[precision], f"drops2048 {precision}")
 
 
+# Largest square grid each storage precision accepts (the 26 population
+# planes of one copy are addressed with 32-bit byte offsets, so they must fit
+# in 4 GiB), and a tile side that divides it.
+MAX_GRID = {"fp64": (4544, 142), "fp32": (6426, 126), "fp16dev": (9088, 142)}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
+def test_largest_grid_equals_its_tiled_small_copy(precision):
+    """The largest grid the library accepts, filled with copies of a small
+    periodic field: every site has the neighbourhood it has in the small
+    run, so after a few steps the large fields are the small ones tiled.
+    Bitwise for float64 and float32 storage; float16 storage draws its
+    rounding bits per site, so there phi, psi and u are held to the float16
+    bar (P, a diagnostic near 1e-8 here, is not under it).  Any offset that
+    overflows at the largest sizes breaks the copy."""
+    n, p = MAX_GRID[precision]
+    steps = 3
+    pr = W.c3_many_drops(precision=precision, nx=p, ny=p, ndrops=2)
+    _, small = run_gpu(pr, precision, steps)
+    reps = (n // p, n // p)
+    sim = lbm.Simulation(dict(pr.params, nx=n, ny=n, precision=precision))
+    sim.init_fields(*[np.tile(a, reps) for a in pr.fields0])
+    sim.step(steps)
+    got = sim.read_fields()
+    sim.close()
+    del sim
+    want = {k: np.tile(small[k], reps) for k in ("phi", "psi", "ux", "uy", "P")}
+    if precision == "fp16dev":
+        err = errors(got, want, FIELDS)
+        assert max(err.values()) <= TOL[precision], err
+    else:
+        for k in want:
+            assert np.array_equal(got[k], want[k]), k
+
+
 def test_tile_height_does_not_change_results():
     """Each site's arithmetic is independent of the tiling: bitwise equal."""
     pr = W.random_small(3, nx=150, ny=70, steps=25)
