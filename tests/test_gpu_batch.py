@@ -152,3 +152,20 @@ def test_autotune_picks_a_valid_schedule_and_keeps_results():
         assert b.remaining(ids[i]) == 0
         assert_same(b.read_fields(ids[i]), alone(p, f, 200), f"tuned sim {i}")
     b.close()
+
+
+@pytest.mark.parametrize("precision,nx,ny", [("fp32", 724, 362), ("fp32", 725, 362),
+                                             ("fp64", 724, 362)])
+def test_cache_resident_size_equals_batch(precision, nx, ny):
+    """A single simulation whose step traffic fits the Infinity Cache
+    (64-320 MB) steps with default stores, a batch always with non-temporal
+    ones: the cache policy changes no result bit."""
+    pr = W.c3_many_drops(precision=precision, nx=nx, ny=ny, ndrops=12)
+    params = dict(pr.params, precision=precision)
+    want = alone(params, pr.fields0, 20)
+    b = lbm.Batch(budget_for([(params, None, 20)]), max_instances=4)
+    i = b.submit(params, *pr.fields0, 20)
+    b.step(20)
+    got = b.read_fields(i)
+    b.close()
+    assert_same(got, want, f"{precision} {nx}x{ny}")
