@@ -2187,9 +2187,12 @@ int default_rows(const lbm_params &p) {
   // Many short tiles keep the wavefronts' start-up and drain phases
   // staggered; the two extra halo rows per tile are served mostly from
   // cache.  Measured on 2048x2048: 2 rows for float32 with two columns per
-  // lane, 3 with one, 4 for float16 and float64 storage.
+  // lane, 3 with one, 5 for float16 storage with two (1% over 4), 4 for
+  // float16 with one and for float64 storage.
   const long long target = p.precision == LBM_FP32 ? 24576 : 16384;
-  const long long lo = p.precision != LBM_FP32 ? 4 : (sites_per_lane(p) == 2 ? 2 : 3);
+  const bool two = sites_per_lane(p) == 2;
+  const long long lo = p.precision == LBM_FP32 ? (two ? 2 : 3)
+                     : p.precision == LBM_FP16DEV && two ? 5 : 4;
   long long rows = strips * p.ny / target;
   if (rows < lo) rows = lo;
   if (rows > 64) rows = 64;
