@@ -206,7 +206,11 @@ void lbm_destroy(lbm_handle *h);
 const char *lbm_last_error(const lbm_handle *h);
 
 /* Rows of lattice each wavefront of the step kernel walks through (its tile
- * height).  0 restores the default.  Errors: LBM_EINVAL (< 0 or > 4096). */
+ * height).  0 restores the default: for a grid too small to fill the
+ * device, the shortest tiles whose wavefronts all fit on it at once (a step
+ * then takes about one wavefront's walk down its tile); otherwise a height
+ * tuned for large grids.  Results do not depend on the tile height.
+ * Errors: LBM_EINVAL (< 0 or > 4096). */
 lbm_status lbm_set_tile_rows(lbm_handle *h, int32_t rows);
 
 /* Name of the device kernel lbm_step launches for this handle (for

@@ -2026,6 +2026,7 @@ struct lbm_handle {
   int rows;
   bool genr, has_s, ns;
   bool resident;  // step stores with the default cache policy (cache_resident)
+  int waves_resident;  // step wavefronts the device holds at once (0: unknown)
   std::string err;
 };
 
@@ -2062,8 +2063,17 @@ int strips_of(const lbm_params &p) {
   return (p.nx + cols - 1) / cols;
 }
 
+// One step launch; with waves_per_cu set, instead the number of this
+// variant's wavefronts one compute unit holds at once.
 template <class P, int K, bool GENR, bool HAS_S, bool NS>
-hipError_t launch_step(lbm_handle *h) {
+hipError_t launch_step(lbm_handle *h, int *waves_per_cu) {
+  if (waves_per_cu) {
+    int blocks = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &blocks, lbm_step_kernel<P, K, GENR, HAS_S, NS>, kWave * P::kBlockWaves, 0);
+    *waves_per_cu = blocks * P::kBlockWaves;
+    return e;
+  }
   StepArgs<P> a;
   a.p = make_phys<typename P::R>(h->p);
   a.sc = make_scales<P>(h->p);
@@ -2085,15 +2095,15 @@ hipError_t launch_step(lbm_handle *h) {
 }
 
 template <class P, int K>
-hipError_t launch_step_prec(lbm_handle *h) {
+hipError_t launch_step_prec(lbm_handle *h, int *waves_per_cu) {
   if (!h->ns)
-    return h->genr ? launch_step<P, K, true, false, false>(h)
-                   : launch_step<P, K, false, false, false>(h);
+    return h->genr ? launch_step<P, K, true, false, false>(h, waves_per_cu)
+                   : launch_step<P, K, false, false, false>(h, waves_per_cu);
   if (h->genr)
-    return h->has_s ? launch_step<P, K, true, true, true>(h)
-                    : launch_step<P, K, true, false, true>(h);
-  return h->has_s ? launch_step<P, K, false, true, true>(h)
-                  : launch_step<P, K, false, false, true>(h);
+    return h->has_s ? launch_step<P, K, true, true, true>(h, waves_per_cu)
+                    : launch_step<P, K, true, false, true>(h, waves_per_cu);
+  return h->has_s ? launch_step<P, K, false, true, true>(h, waves_per_cu)
+                  : launch_step<P, K, false, false, true>(h, waves_per_cu);
 }
 
 template <class P, int K, bool GENR, bool HAS_S, bool NS>
@@ -2126,15 +2136,16 @@ void launch_batch_prec(int c, int blocks, hipStream_t st, const void *desc,
 // height; the float32 and float64 kernels keep fused multiply-adds (1-2%
 // faster) and are tile-height independent with them.
 namespace lbm_f16_part {
-hipError_t step(lbm_handle *h);
+hipError_t step(lbm_handle *h, int *waves_per_cu);
 void batch(int c, int blocks, hipStream_t st, const void *desc, const void *tiles,
            const int *count, int k);
 }  // namespace lbm_f16_part
 
 #ifdef LBM_F16_PART
 namespace lbm_f16_part {
-hipError_t step(lbm_handle *h) {
-  return sites_per_lane(h->p) == 2 ? launch_step_prec<F16, 2>(h) : launch_step_prec<F16, 1>(h);
+hipError_t step(lbm_handle *h, int *waves_per_cu) {
+  return sites_per_lane(h->p) == 2 ? launch_step_prec<F16, 2>(h, waves_per_cu)
+                                   : launch_step_prec<F16, 1>(h, waves_per_cu);
 }
 void batch(int c, int blocks, hipStream_t st, const void *desc, const void *tiles,
            const int *count, int k) {
@@ -2200,16 +2211,46 @@ int default_rows(const lbm_params &p) {
 }
 
 
-hipError_t run_step(lbm_handle *h) {
+// One step of h (or, with waves_per_cu set, the occupancy of its kernel).
+hipError_t run_step(lbm_handle *h, int *waves_per_cu = nullptr) {
+  int *w = waves_per_cu;
   switch (h->p.precision) {
     case LBM_FP64:
-      return h->resident ? launch_step_prec<F64C, 1>(h) : launch_step_prec<F64, 1>(h);
+      return h->resident ? launch_step_prec<F64C, 1>(h, w) : launch_step_prec<F64, 1>(h, w);
     case LBM_FP32:
       if (sites_per_lane(h->p) == 2)
-        return h->resident ? launch_step_prec<F32C, 2>(h) : launch_step_prec<F32, 2>(h);
-      return h->resident ? launch_step_prec<F32C, 1>(h) : launch_step_prec<F32, 1>(h);
-    default: return lbm_f16_part::step(h);
+        return h->resident ? launch_step_prec<F32C, 2>(h, w) : launch_step_prec<F32, 2>(h, w);
+      return h->resident ? launch_step_prec<F32C, 1>(h, w) : launch_step_prec<F32, 1>(h, w);
+    default: return lbm_f16_part::step(h, w);
   }
+}
+
+// Default tile height of a single simulation.  A step costs about one
+// wavefront's walk down its tile (3-5 us per row) when every wavefront of
+// the launch fits on the device at once, so a grid too small to fill the
+// device takes the shortest tiles that still fit in one round (measured:
+// 1-row tiles make a 64x64 step 1.5-3x faster than the heights tuned for
+// large grids).  Larger grids keep those heights (default_rows).
+int single_rows(const lbm_handle *h) {
+  const int lo = default_rows(h->p);
+  const long long strips = strips_of(h->p);
+  if (h->waves_resident <= 0) return lo;
+  for (int r = 1; r < lo; ++r)
+    if (strips * ((h->p.ny + r - 1) / r) <= h->waves_resident) return r;
+  return lo;
+}
+
+// Wavefronts of h's step kernel the current device holds at once (0 if the
+// runtime cannot tell).
+int query_waves_resident(lbm_handle *h) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      run_step(h, &per_cu) != hipSuccess) {
+    (void)hipGetLastError();  // leave no error behind for the next call
+    return 0;
+  }
+  return cus * per_cu;
 }
 
 template <class P>
@@ -2302,6 +2343,8 @@ lbm_status lbm_create(const lbm_params *params, void *dev_ws, size_t ws_bytes,
   h->ns = params->flow == LBM_FLOW_NS;
   h->has_s = h->ns && params->rhoA != params->rhoB;
   h->resident = cache_resident(*params);
+  h->waves_resident = query_waves_resident(h);
+  h->rows = single_rows(h);
   *out = h;
   return LBM_OK;
 }
@@ -2521,7 +2564,7 @@ const char *lbm_last_error(const lbm_handle *h) {
 lbm_status lbm_set_tile_rows(lbm_handle *h, int32_t rows) {
   if (!h) return LBM_EINVAL;
   if (rows < 0 || rows > 4096) return fail(h, LBM_EINVAL, "rows out of range");
-  h->rows = rows == 0 ? default_rows(h->p) : rows;
+  h->rows = rows == 0 ? single_rows(h) : rows;
   return LBM_OK;
 }
 
