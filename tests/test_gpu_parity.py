@@ -151,7 +151,7 @@ def test_tile_height_does_not_change_results_reduced(precision, nx):
     (odd nx): every tile height gives the same bits."""
     pr = W.random_small(5, nx=nx, ny=40, walls=True, steps=15)
     outs = []
-    for rows in (1, 3, 7, 40):
+    for rows in (1, 3, 7, 40, 0):  # 0: the default (small grid: the shortest fitting tiles)
         _, got = run_gpu(pr, precision, pr.steps, rows=rows)
         outs.append(got)
     for o in outs[1:]:
@@ -218,7 +218,7 @@ def test_tile_height_does_not_change_results():
     """Each site's arithmetic is independent of the tiling: bitwise equal."""
     pr = W.random_small(3, nx=150, ny=70, steps=25)
     outs = []
-    for rows in (1, 3, 8, 70, 200):
+    for rows in (1, 3, 8, 70, 200, 0):
         _, got = run_gpu(pr, "fp64", pr.steps, rows=rows)
         outs.append(got)
     for o in outs[1:]:
