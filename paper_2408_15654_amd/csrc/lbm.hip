@@ -1111,6 +1111,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     for (int k = 0; k < K; ++k) dst[k] = src[k];
   };
 
+  // Prologue: phi, psi, sigma of rows y0 and y0-1, and the loop's first
+  // prefetch.  With float32 and float64 storage every load is issued before
+  // the first rebuild, so a tile starts after one round trip to memory
+  // rather than three (1% faster on the 2048x2048 field for float64, 4-10%
+  // shorter steps on grids too small to fill the device).  Float16 storage
+  // keeps the rebuilds between the loads (3% faster there).
+  constexpr bool kEarlyLoads = !P::SCALED;
   // old rest values of this lane's columns, rows y-1 .. y+2
   R X0[K], X1[K], X2[K], X3[K], Y0[K], Y1[K], Y2[K], Y3[K];
   rest_at(y0 - 1, X0, Y0);
@@ -1120,17 +1127,32 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   R dc[K][9], qc[K][9];
   R phc[K], psc[K], sgc[K], phm[K], psm[K], sgm[K];
   load_fg(y0, dc, qc);
-  rebuild(y0, X0, X1, X2, Y0, Y1, Y2, dc, qc, phc, psc, sgc);
-  if (walls && y0 == 0) {  // mirror ghost row below the bottom wall
-    copy(phm, phc);
-    copy(psm, psc);
-    copy(sgm, sgc);
+  // row y0-1, unless it is the mirror ghost below the bottom wall
+  const bool ghost_below = walls && y0 == 0;
+  const int ym = y0 == 0 ? ny - 1 : y0 - 1;
+  R dt[K][9], qt[K][9], Xa[K], Ya[K];
+  auto load_below = [&]() {
+    if (!ghost_below) {
+      rest_at(y0 - 2, Xa, Ya);
+      load_fg(ym, dt, qt);
+    }
+  };
+  auto rebuild_y0 = [&]() { rebuild(y0, X0, X1, X2, Y0, Y1, Y2, dc, qc, phc, psc, sgc); };
+  auto rebuild_below = [&]() {
+    if (ghost_below) {
+      copy(phm, phc);
+      copy(psm, psc);
+      copy(sgm, sgc);
+    } else {
+      rebuild(ym, Xa, X0, X1, Ya, Y0, Y1, dt, qt, phm, psm, sgm);
+    }
+  };
+  if (kEarlyLoads) {
+    load_below();
   } else {
-    R dt[K][9], qt[K][9], Xa[K], Ya[K];
-    const int ym = y0 == 0 ? ny - 1 : y0 - 1;
-    rest_at(y0 - 2, Xa, Ya);
-    load_fg(ym, dt, qt);
-    rebuild(ym, Xa, X0, X1, Ya, Y0, Y1, dt, qt, phm, psm, sgm);
+    rebuild_y0();
+    load_below();
+    rebuild_below();
   }
 
   // Software pipeline: the loads for row y+1 are issued before the
@@ -1152,6 +1174,11 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     hrest_at(y0 - 1, Hm);
     hrest_at(y0, Hc);
     hrest_at(y0 + 1, Hn);
+  }
+
+  if (kEarlyLoads) {
+    rebuild_y0();
+    rebuild_below();
   }
 
   // Stores are issued by every lane: a halo lane repeats lane HL's values
