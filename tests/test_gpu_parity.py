@@ -117,6 +117,17 @@ def test_random_small_fp32(seed):
     check(got, want, 1e-5, f"random{seed} fp32")
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_fp16dev(seed):
+    """Float16-deviation storage on the random problems (walls or periodic,
+    r in {0, 1, 2}, linear or Langmuir EOS, density ratios, body force, odd
+    and even widths): within the float16 bar after 60 steps."""
+    pr = W.random_small(seed, steps=60)
+    _, got = run_gpu(pr, "fp16dev", pr.steps)
+    _, want = run_oracle(pr, pr.steps)
+    check(got, want, TOL["fp16dev"], f"random{seed} fp16dev")
+
+
 @pytest.mark.parametrize("nx,ny", [(3, 3), (5, 4), (61, 7), (62, 9), (63, 5), (64, 3),
                                    (125, 11), (186, 6)])
 def test_ragged_and_tiny_grids(nx, ny):
