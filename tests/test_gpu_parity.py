@@ -109,7 +109,7 @@ def test_random_small_fp64(seed):
           FIELDS + ("P",))
 
 
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", range(8))
 def test_random_small_fp32(seed):
     pr = W.random_small(seed, steps=60)
     _, got = run_gpu(pr, "fp32", pr.steps)
@@ -311,26 +311,29 @@ def test_prescribed_convection_full_run(precision):
     assert np.abs(got["P"]).max() == 0.0
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
 @pytest.mark.parametrize("seed", range(4))
-def test_prescribed_random_small_fp64(seed):
-    """Random sizes, walls, r, EOS, with a smooth prescribed velocity field.
-    (A velocity drawn independently per site makes some of these problems
-    amplify a 1e-15 perturbation to 1e-10 in the oracle alone.)"""
+def test_prescribed_random_small(seed, precision):
+    """Random sizes, walls, r, EOS, with a smooth prescribed velocity field,
+    in every storage precision.  (A velocity drawn independently per site
+    makes some of these problems amplify a 1e-15 perturbation to 1e-10 in
+    the oracle alone.)"""
     pr = W.random_small(200 + seed, steps=40)
     ny, nx = pr.phi0.shape
     y, x = np.mgrid[0:ny, 0:nx]
     ux = 0.04 * np.sin(2 * np.pi * y / ny + seed)
     uy = 0.03 * np.cos(2 * np.pi * x / nx + 2 * seed)
     params = dict(pr.params, flow="prescribed")
-    sim = lbm.Simulation(dict(params, precision="fp64"))
+    sim = lbm.Simulation(dict(params, precision=precision))
     sim.init_fields(pr.phi0, pr.psi0, ux, uy)
     sim.step(pr.steps)
     got = sim.read_fields()
+    sim.close()
     ref = O.OracleSim(params, pr.phi0, pr.psi0, ux, uy)
     ref.step(pr.steps)
     want = ref.fields()
-    check(got, want, 1e-12, f"prescribed random{seed} {params['nx']}x{params['ny']} "
-          f"walls={params['walls_y']} r={params['r']}")
+    check(got, want, TOL[precision], f"prescribed random{seed} {precision} "
+          f"{params['nx']}x{params['ny']} walls={params['walls_y']} r={params['r']}")
 
 
 # ------------------------------------------------ shape diagnostics
