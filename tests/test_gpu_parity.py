@@ -237,9 +237,10 @@ def test_tile_height_does_not_change_results():
             assert np.array_equal(o[k], outs[0][k]), k
 
 
-def test_checkpoint_restore_is_bitwise():
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
+def test_checkpoint_restore_is_bitwise(precision):
     pr = W.random_small(4, steps=30)
-    sim = lbm.Simulation(dict(pr.params, precision="fp32"))
+    sim = lbm.Simulation(dict(pr.params, precision=precision))
     sim.init_fields(*pr.fields0)
     sim.step(10)
     state = sim.get_state()
@@ -250,8 +251,16 @@ def test_checkpoint_restore_is_bitwise():
     assert sim.moments()["step"] == 10
     sim.step(20)
     b = sim.read_fields()
+    sim.close()
+    # the state is self-contained: a fresh handle continues the same way
+    fresh = lbm.Simulation(dict(pr.params, precision=precision))
+    fresh.set_state(state)
+    fresh.step(20)
+    c = fresh.read_fields()
+    fresh.close()
     for k in ("phi", "psi", "ux", "uy", "P"):
         assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
 
 
 def test_nonfinite_is_reported_and_blocks_stepping():
