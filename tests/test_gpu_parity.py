@@ -347,14 +347,21 @@ def test_prescribed_random_small(seed, precision):
 
 # ------------------------------------------------ shape diagnostics
 
-def test_shape_diagnostics_match_the_oracle():
+# shape quantities against the oracle's: the step's own bar carried over
+# (relative, or absolute below 1), loosened for the derived quantities
+SHAPE_TOL = {"fp64": 1e-10, "fp32": 1e-4, "fp16dev": 1e-2}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
+def test_shape_diagnostics_match_the_oracle(precision):
     """lbm_shape (device float64 reductions) against the plain numpy
     diagnostics: on the library's own read-back phi (same input: the
-    reductions alone) and on the oracle's phi of the same run."""
+    reductions alone, to 1e-12 in every precision) and on the oracle's phi
+    of the same run."""
     import shape as SH
 
     pr = W.c2_shear_drop(beta=0.5)
-    sim = lbm.Simulation(dict(pr.params, precision="fp64"))
+    sim = lbm.Simulation(dict(pr.params, precision=precision))
     sim.init_fields(*pr.fields0)
     sim.step(300)
     got = sim.shape()
@@ -364,7 +371,7 @@ def test_shape_diagnostics_match_the_oracle():
     for k in mine:
         scale = max(abs(mine[k]), 1.0)
         assert abs(got[k] - mine[k]) <= 1e-12 * scale, (k, got[k], mine[k])
-        assert abs(got[k] - want[k]) <= 1e-10 * scale, (k, got[k], want[k])
+        assert abs(got[k] - want[k]) <= SHAPE_TOL[precision] * scale, (k, got[k], want[k])
     assert 0.0 < got["taylor_D"] < 0.5 and got["length"] > 2 * np.pi * 32 * 0.95
     sim.close()
 
