@@ -376,7 +376,7 @@ def test_shape_diagnostics_match_the_oracle(precision):
     sim.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
 def test_rising_bubble_small(precision):
     """Buoyant bubble between walls (Sec. 4.3 geometry, 40x80), 400 steps,
     with surfactant (beta 0.5).  g = 5e-6: at g = 2e-5 this small problem
