@@ -213,8 +213,12 @@ const char *lbm_last_error(const lbm_handle *h);
  * Errors: LBM_EINVAL (< 0 or > 4096). */
 lbm_status lbm_set_tile_rows(lbm_handle *h, int32_t rows);
 
-/* Name of the device kernel lbm_step launches for this handle (for
- * profiler look-ups). */
+/* The step kernel variant lbm_step launches for this handle, named as a
+ * profiler prints its template arguments, e.g.
+ * "lbm_step_kernel<F32, 2, false, true, true>": storage (F64, F32, F16; F64C
+ * and F32C store with the default cache policy), columns per lane, r != 1,
+ * rho_A != rho_B, Navier-Stokes velocity.  Valid while the handle lives;
+ * "lbm_step_kernel" for a NULL handle. */
 const char *lbm_step_kernel_name(const lbm_handle *h);
 
 /* ----------------------------------------------------------------------

@@ -2054,6 +2054,7 @@ struct lbm_handle {
   bool genr, has_s, ns;
   bool resident;  // step stores with the default cache policy (cache_resident)
   int waves_resident;  // step wavefronts the device holds at once (0: unknown)
+  std::string kernel;  // the step kernel variant, as a profiler names it
   std::string err;
 };
 
@@ -2269,6 +2270,18 @@ int single_rows(const lbm_handle *h) {
   return lo;
 }
 
+// The template arguments of the step kernel run_step launches for h, in the
+// order a profiler prints them: storage, columns per lane, r != 1,
+// rho_A != rho_B, Navier-Stokes velocity.
+std::string kernel_name_of(const lbm_handle *h) {
+  const char *prec = h->p.precision == LBM_FP64   ? (h->resident ? "F64C" : "F64")
+                     : h->p.precision == LBM_FP32 ? (h->resident ? "F32C" : "F32")
+                                                  : "F16";
+  auto b = [](bool v) { return v ? "true" : "false"; };
+  return std::string("lbm_step_kernel<") + prec + ", " + std::to_string(sites_per_lane(h->p)) +
+         ", " + b(h->genr) + ", " + b(h->has_s) + ", " + b(h->ns) + ">";
+}
+
 // Wavefronts of h's step kernel the current device holds at once (0 if the
 // runtime cannot tell).
 int query_waves_resident(lbm_handle *h) {
@@ -2374,6 +2387,7 @@ lbm_status lbm_create(const lbm_params *params, void *dev_ws, size_t ws_bytes,
   h->resident = cache_resident(*params);
   h->waves_resident = query_waves_resident(h);
   h->rows = single_rows(h);
+  h->kernel = kernel_name_of(h);
   *out = h;
   return LBM_OK;
 }
@@ -2598,8 +2612,7 @@ lbm_status lbm_set_tile_rows(lbm_handle *h, int32_t rows) {
 }
 
 const char *lbm_step_kernel_name(const lbm_handle *h) {
-  (void)h;
-  return "lbm_step_kernel";
+  return h ? h->kernel.c_str() : "lbm_step_kernel";
 }
 
 }  // extern "C"

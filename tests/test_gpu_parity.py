@@ -385,3 +385,21 @@ def test_rising_bubble_small(precision):
     _, got = run_gpu(pr, precision, pr.steps)
     _, want = run_oracle(pr, pr.steps)
     check(got, want, TOL[precision], f"bubble40 {precision}")
+
+
+def test_step_kernel_name_names_the_variant():
+    """lbm_step_kernel_name gives the template arguments of the kernel
+    lbm_step launches: storage (the cache-resident variants for 64-320 MB of
+    step traffic), columns per lane, r != 1, rho_A != rho_B, Navier-Stokes."""
+    cases = [
+        (W.c3_many_drops(precision="fp32"), "fp32", "lbm_step_kernel<F32, 2, false, true, true>"),
+        (W.c3_many_drops(precision="fp32", nx=724, ny=362, ndrops=12), "fp32",
+         "lbm_step_kernel<F32C, 2, false, true, true>"),
+        (W.c1_stationary_drop(), "fp64", "lbm_step_kernel<F64, 1, true, false, true>"),
+        (W.c1_stationary_drop(), "fp16dev", "lbm_step_kernel<F16, 2, true, false, true>"),
+        (W.e2_convection(nx=101), "fp32", "lbm_step_kernel<F32, 1, false, false, false>"),
+    ]
+    for pr, prec, want in cases:
+        sim = lbm.Simulation(dict(pr.params, precision=prec))
+        assert sim.step_kernel_name() == want, (prec, pr.params["nx"], sim.step_kernel_name())
+        sim.close()
