@@ -57,10 +57,13 @@
  *     given initial field at every level, P = 0, only f and g evolve; the
  *     time differences become (phi - phi_prev) u and (psi - psi_prev) u.
  *
- * Parity unpinned: the factor K = 2/3 in front of the time-difference term
- * tr d_t(rho uu - (Su+uS)/2) of the pressure, Eq. (32b).  No test fixes it
- * independently (changing it moves no pinned quantity beyond its tolerance);
- * it follows the paper's statement of P as read above.
+ * Every part is pinned by a test against a fact outside this file
+ * (conservation, closed forms, moment conditions, symmetries, Laplace's
+ * law, uniform acceleration, layered Couette flow).  In particular the
+ * factor K = w0/(c^2 - c_s^2) of Eq. (32b) is fixed by the pressure of a
+ * uniformly accelerated fluid staying constant, the Langmuir law (19) by
+ * the Laplace jump of a drop with uniform surfactant, and the wall density
+ * of the moving-wall term by no-slip Couette flow of a dense layer.
  */
 #include <math.h>
 #include <omp.h>

@@ -383,6 +383,45 @@ def test_couette_exact_with_moving_walls(mu):
     assert np.abs(fl["uy"]).max() < 1e-15
 
 
+@pytest.mark.parametrize("rhoA,muA,rhoB,muB", [(10.0, 1.0, 1.0, 0.1), (3.0, 0.2, 1.0, 1.0)])
+def test_layered_couette_with_density_contrast(rhoA, muA, rhoB, muB):
+    """Moving walls under a density contrast (Sec. 4, half-way bounce-back
+    of Ladd): a layer of fluid A on the bottom wall (wall speed -U) under a
+    layer of fluid B (top wall +U).  The steady state is plane Couette flow
+    with one shear stress tau throughout, so the wall speeds are met with
+    no slip and mu du/dy = tau = 2U / int dy/mu in the bulk of each layer.
+    The momentum a moving wall gives a reflected population is proportional
+    to the density of the fluid at the wall (rho_w = rho(phi) of the
+    boundary site); with rho_w = 1 or rho_B next to fluid A the wall would
+    drag fluid A at a fraction of its speed."""
+    nx, ny, U = 4, 32, 0.01
+    p = W.base_params(nx, ny, walls_y=1, u_wall_bot=-U, u_wall_top=U, rhoA=rhoA,
+                      rhoB=rhoB, muA=muA, muB=muB, sigma0=0.0)
+    y = np.arange(ny, dtype=float)[:, None] * np.ones((1, nx))
+    phi = W.tanh_profile(12.0 - y, 4.0)
+    z = np.zeros_like(phi)
+    s = O.OracleSim(p, phi, W.unit_peak(phi), z, z)
+    s.step(60000)
+    fl = s.fields()
+    u = fl["ux"][:, 0]
+    assert np.abs(fl["ux"] - u[:, None]).max() < 1e-12 * U
+    assert np.abs(fl["uy"]).max() < 1e-3 * U
+    # no slip: linear extrapolation of the two nearest sites to the wall
+    # plane (half a site outside) gives the wall speed (the lattice slip
+    # of half-way bounce-back at these rates is below 0.4 % of U; a wall
+    # density of 1 or rho_B next to fluid A slips by 65-90 %)
+    assert abs(1.5 * u[0] - 0.5 * u[1] + U) < 1e-2 * U
+    assert abs(1.5 * u[-1] - 0.5 * u[-2] - U) < 1e-2 * U
+    # one shear stress: mu du/dy in the bulk of each layer, against the
+    # continuum value with the sites' mu (the diffuse interface shifts it
+    # by up to 3 %; the wrong wall densities by 33-45 %)
+    mu = muB + fl["phi"][:, 0] * (muA - muB)
+    tau = 2 * U / (1.0 / mu).sum()
+    stress = mu[:-1] * np.diff(u)
+    for rows in (slice(1, 4), slice(24, 30)):
+        np.testing.assert_allclose(stress[rows], tau, rtol=0.05)
+
+
 def _psi_mode(fl, cx, cy):
     ny, nx = fl["psi"].shape
     y, x = np.mgrid[0:ny, 0:nx]
@@ -472,6 +511,67 @@ def test_stationary_drop_laplace_and_spurious_currents():
     ratio = res[0.3][0] / dP0
     expect = 1 - 0.8 * 0.3 * res[0.3][1]
     assert abs(ratio / expect - 1) < 0.02
+
+
+@pytest.mark.slow
+def test_langmuir_tension_sets_the_laplace_jump():
+    """Langmuir equation of state, Eq. (19): sigma = sigma0 [1 + E_0 ln(1 -
+    psi)].  For a drop at rest with psi uniform along its rim, the Marangoni
+    part of Eq. (18) vanishes (grad sigma is parallel to grad phi) and the
+    capillary part integrates across the interface to Laplace's jump
+    dP = sigma_eff / R, where sigma_eff is sigma(psi) averaged across the
+    interface with the weight |grad phi|^2 of the capillary term (for the
+    profile (7) that weight is sech^4).  Relative to the clean drop the jump
+    therefore scales by sigma_eff / sigma0, which the test forms from the
+    final psi and phi fields and the printed Eq. (19).  A sign slip, log(1 +
+    psi) or the linearised law -psi each move the ratio by 4 % or more."""
+
+    def grad2(a):
+        gx = 0.5 * (np.roll(a, -1, 1) - np.roll(a, 1, 1))
+        gy = 0.5 * (np.roll(a, -1, 0) - np.roll(a, 1, 0))
+        return gx * gx + gy * gy
+
+    def jump(beta, psi0, eos):
+        pr = W.c1_stationary_drop(beta=beta, psi_mode=0.0, r=1.0, eos=eos)
+        s = O.OracleSim(pr.params, pr.phi0, psi0 * pr.psi0, pr.ux0, pr.uy0)
+        s.step(6000)
+        fl = s.fields()
+        P = fl["P"]
+        return P[30:35, 30:35].mean() - P[0:3, 0:3].mean(), fl
+
+    clean, _ = jump(0.0, 1.0, "linear")
+    assert 0.90 < clean * 16 / 1e-3 < 1.05
+    for beta, psi0 in ((0.3, 0.5), (0.4, 0.6)):
+        dP, fl = jump(beta, psi0, "langmuir")
+        w = grad2(fl["phi"])
+        sigma_eff = ((1.0 + beta * np.log(1.0 - fl["psi"])) * w).sum() / w.sum()
+        assert abs(dP / clean / sigma_eff - 1) < 0.015, (beta, psi0, dP / clean, sigma_eff)
+
+
+def test_pressure_stays_constant_under_uniform_acceleration():
+    """Eq. (32b) with K = w0 / (c^2 - c_s^2) (Sec. 4): a uniform single-phase
+    fluid pushed by a uniform body force accelerates as a whole and, in the
+    frame moving with it, stays at rest and uniform, so its pressure must
+    not change.  The time-difference term K dt/2 d_t(rho u.u) of Eq. (32b)
+    is what cancels the growth of the kinetic part of sum_{i!=0} h_i.  On
+    the lattice the pressure then moves only at the next order, O(rho g u)
+    per unit time; with K = 0 it would fall by about rho |u|^2 / 5, with the
+    sign of the term reversed by 2 rho |u|^2 / 5.  Checked for three
+    viscosities (tau_f = 1, 0.8, 2) and two force directions after 1000
+    steps, |P| <= 1e-2 rho |u|^2."""
+    for mu in (1.0 / 6.0, 0.1, 0.5):
+        for g in ((1e-5, 0.0), (3e-6, -4e-6)):
+            p = W.base_params(4, 4, sigma0=0.0, gx=g[0], gy=g[1], rhoA=1.0, rhoB=1.0,
+                              muA=mu, muB=mu)
+            z = np.zeros((4, 4))
+            s = O.OracleSim(p, z, z, z, z)
+            s.step(1000)
+            fl = s.fields()
+            u2 = fl["ux"] ** 2 + fl["uy"] ** 2
+            # the fluid did accelerate: u = g (t + 1/2) (Eq. (32a))
+            np.testing.assert_allclose(fl["ux"], g[0] * 1000.5, rtol=1e-9)
+            np.testing.assert_allclose(fl["uy"], g[1] * 1000.5, rtol=1e-9)
+            assert np.abs(fl["P"]).max() <= 1e-2 * u2.min(), (mu, g, fl["P"].max(), u2.min())
 
 
 def test_marangoni_drives_drop_toward_low_tension():
