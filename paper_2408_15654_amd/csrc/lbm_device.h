@@ -39,6 +39,32 @@ struct Phys {
   int eos;                 // 0 linear, 1 Langmuir
 };
 
+// x/3 and x/9.  In float32 the rounded reciprocals are biased (1/3 by
+// +3.0e-8 relative), and the third-order equilibrium moments rho u/3 and
+// X u/3 of the collisions are large terms whose differences make the
+// viscous stress and the diffusive flux: the bias changes the effective
+// viscosity by parts per million and the error of a decaying flow then
+// grows step after step (to 2.6e-5 of u over 5000 steps of the 2048x2048
+// field).  Adding the product with the reciprocal's remainder in one fused
+// multiply-add leaves only the product's unbiased rounding.  float64 keeps
+// the plain product (bias 2e-17).
+template <class R>
+__device__ __forceinline__ R third_of(R x) {
+  return x * (R(1) / R(3));
+}
+template <>
+__device__ __forceinline__ float third_of<float>(float x) {
+  return __builtin_fmaf(x, 0x1.555556p-2f, x * -0x1.555556p-27f);
+}
+template <class R>
+__device__ __forceinline__ R ninth_of(R x) {
+  return x * (R(1) / R(9));
+}
+template <>
+__device__ __forceinline__ float ninth_of<float>(float x) {
+  return __builtin_fmaf(x, 0x1.c71c72p-4f, x * -0x1.c71c72p-31f);
+}
+
 template <class R>
 __device__ __forceinline__ R rho_of(const Phys<R>& p, R phi) {
   return p.rhoB + p.drho * (phi - p.phiB);
@@ -130,11 +156,15 @@ __device__ __forceinline__ void site_front(const Phys<R>& p, Front<R>& s, R phi,
   } else {
     s.Sx = s.Sy = s.grx = s.gry = R(0);
   }
-  // first moment and sum of h_1..h_8 (h[k] holds h_{k+1})
+  // first moment and sum of h_1..h_8 (h[k] holds h_{k+1}).  The sum pairs
+  // opposite directions first: each h_i carries 3 w_i c_i . rho u (Eq.
+  // (30)), far larger than the pressure the sum leaves, and the pair sums
+  // cancel those parts exactly (nearly equal magnitudes), so P keeps the
+  // precision of its own size rather than that of rho u.
   const R d57 = h[4] - h[6], d68 = h[5] - h[7];
   const R jx0 = (h[0] - h[2]) + (d57 - d68);
   const R jy0 = (h[1] - h[3]) + (d57 + d68);
-  const R sumh = ((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7]));
+  const R sumh = ((h[0] + h[2]) + (h[1] + h[3])) + ((h[4] + h[6]) + (h[5] + h[7]));
   s.jx = jx0 + R(0.5) * s.Fx;
   s.jy = jy0 + R(0.5) * s.Fy;
   const R irho = R(1) / rho;
@@ -173,16 +203,20 @@ __device__ __forceinline__ void site_front(const Phys<R>& p, Front<R>& s, R phi,
 
 // MRT collision of a convection-diffusion LB (Eqs. (21), (25)) in raw-moment
 // space, on DEVIATIONS d_i = f_i - w_i X from the rest equilibrium of the
-// site's own value X = sum f_i.  The rest part w_i X has moments
+// site's value X (the zeroth moment rounded to the arithmetic type; the
+// deviations carry the rounding remainder as their zeroth moment m0, so
+// X + m0 = sum f_i).  The rest part w_i X has moments
 // (X, 0, 0, X/3, X/3, 0, 0, 0, X/9), all of which the collision keeps, so
 // only the deviations are relaxed:
 //   m_eq - m_rest = (0, X ux, X uy, 0, 0, 0, X ux/3, X uy/3, 0),
 //   m_F           = (0, Vx/3, Vy/3, 0, 0, 0, Vx/9, Vy/9, 0),
 // with the source w_i c_i.V, V = 3 d_t(X u) + (flux term).  Rates s1 (first
-// moments), s2 (second), s3 (third), s4 (fourth).  The post-collision
-// zeroth deviation moment is 0 (m0 = X is conserved).  In place on d[0..8].
-// Working on deviations keeps every intermediate small, so low-precision
-// arithmetic and storage lose little absolute accuracy.
+// moments), s2 (second), s3 (third), s4 (fourth).  The zeroth moment is
+// conserved, remainder m0 included, so no rounding of X is ever lost from
+// the sum of X (a change of X far below its last bit accumulates in m0
+// until it shows).  In place on d[0..8].  Working on deviations keeps every
+// intermediate small, so low-precision arithmetic and storage lose little
+// absolute accuracy.
 template <class R>
 __device__ __forceinline__ void collide_cde(R* d, R X, R ux, R uy, R Vx, R Vy,
                                             R s1, R s2, R s3, R s4) {
@@ -192,19 +226,19 @@ __device__ __forceinline__ void collide_cde(R* d, R X, R ux, R uy, R Vx, R Vy,
   R m6 = d57 - d68, m7 = d57 + d68;
   R m1 = (d[1] - d[3]) + m6, m2 = (d[2] - d[4]) + m7;
   R m3 = (d[1] + d[3]) + m8, m4 = (d[2] + d[4]) + m8;
-  const R third = R(1) / R(3), ninth = R(1) / R(9);
+  const R m0 = (d[0] + (m3 + m4)) - m8;  // sum of the incoming d_i
   const R Xux = X * ux, Xuy = X * uy;
   const R h1 = R(1) - R(0.5) * s1, h3 = R(1) - R(0.5) * s3;
-  m1 = m1 - s1 * (m1 - Xux) + h1 * (Vx * third);
-  m2 = m2 - s1 * (m2 - Xuy) + h1 * (Vy * third);
+  m1 = m1 - s1 * (m1 - Xux) + h1 * third_of(Vx);
+  m2 = m2 - s1 * (m2 - Xuy) + h1 * third_of(Vy);
   m3 = m3 - s2 * m3;
   m4 = m4 - s2 * m4;
   m5 = m5 - s2 * m5;
-  m6 = m6 - s3 * (m6 - Xux * third) + h3 * (Vx * ninth);
-  m7 = m7 - s3 * (m7 - Xuy * third) + h3 * (Vy * ninth);
+  m6 = m6 - s3 * (m6 - third_of(Xux)) + h3 * ninth_of(Vx);
+  m7 = m7 - s3 * (m7 - third_of(Xuy)) + h3 * ninth_of(Vy);
   m8 = m8 - s4 * m8;
-  // d = M^-1 m with m0 = 0
-  d[0] = -m3 - m4 + m8;
+  // d = M^-1 m
+  d[0] = m0 - m3 - m4 + m8;
   d[1] = R(0.5) * (m1 + m3 - m6 - m8);
   d[2] = R(0.5) * (m2 + m4 - m7 - m8);
   d[3] = R(0.5) * (-m1 + m3 + m6 - m8);
@@ -219,9 +253,12 @@ __device__ __forceinline__ void collide_cde(R* d, R X, R ux, R uy, R Vx, R Vy,
 // source site s_i with stored deviation dsrc_i (relative to w_i X(s_i)); e_i
 // = X(s_i) - Xc is the source's rest value relative to the site's own old
 // value Xc.  The new zeroth moment is
-//   X' = sum_i (w_i X(s_i) + dsrc_i) = Xc + sum_i w_i e_i + sum_i dsrc_i
-// and the deviations relative to w_i X' are dsrc_i + w_i (e_i - (X' - Xc)).
-// Everything except the final X' is formed from small differences.
+//   X' = sum_i (w_i X(s_i) + dsrc_i) = Xc + sum_i w_i e_i + sum_i dsrc_i,
+// formed from small differences as Xc + dX and rounded.  The deviations are
+// taken relative to w_i times that ROUNDED value, dsrc_i + w_i (e_i - dR),
+// dR = round(Xc + dX) - Xc (exact for nearby values), so they sum to the
+// rounding remainder dX - dR instead of dropping it: the stored state keeps
+// the sum of X exactly, whatever the precision of X.
 template <class R>
 __device__ __forceinline__ R restream(R* d, const R* e, R Xc) {
   const R w0 = R(4) / R(9), w1 = R(1) / R(9), w5 = R(1) / R(36);
@@ -229,12 +266,14 @@ __device__ __forceinline__ R restream(R* d, const R* e, R Xc) {
                w5 * ((e[5] + e[6]) + (e[7] + e[8]));
   const R sd = ((d[0] + (d[1] + d[2])) + (d[3] + d[4])) + ((d[5] + d[6]) + (d[7] + d[8]));
   const R dX = se + sd;
-  d[0] += w0 * (e[0] - dX);
+  const R Xn = Xc + dX;
+  const R dR = Xn - Xc;
+  d[0] += w0 * (e[0] - dR);
 #pragma unroll
-  for (int i = 1; i < 5; ++i) d[i] += w1 * (e[i] - dX);
+  for (int i = 1; i < 5; ++i) d[i] += w1 * (e[i] - dR);
 #pragma unroll
-  for (int i = 5; i < 9; ++i) d[i] += w5 * (e[i] - dX);
-  return Xc + dX;
+  for (int i = 5; i < 9; ++i) d[i] += w5 * (e[i] - dR);
+  return Xn;
 }
 
 // MRT collision of the flow LB (Eq. (29)) on h_1..h_8 (h[k] = h_{k+1}),
@@ -253,24 +292,23 @@ __device__ __forceinline__ void collide_flow(R* h, const Front<R>& s, R s3, R s4
   R m6 = d57 - d68, m7 = d57 + d68;
   R m1 = (h[0] - h[2]) + m6, m2 = (h[1] - h[3]) + m7;
   R m3 = (h[0] + h[2]) + m8, m4 = (h[1] + h[3]) + m8;
-  const R third = R(1) / R(3), ninth = R(1) / R(9);
   const R ux = s.ux, uy = s.uy;
   const R Ax = s.jx - s.Sx, Ay = s.jy - s.Sy;
   const R Au = Ax * ux + Ay * uy;
   const R B = ux * s.grx + uy * s.gry;
-  const R mxx = s.dTxx + R(2) * third * ux * s.grx;
-  const R myy = s.dTyy + R(2) * third * uy * s.gry;
-  const R mxy = s.dTxy + third * (ux * s.gry + uy * s.grx);
+  const R mxx = s.dTxx + third_of(R(2) * ux * s.grx);
+  const R myy = s.dTyy + third_of(R(2) * uy * s.gry);
+  const R mxy = s.dTxy + third_of(ux * s.gry + uy * s.grx);
   const R s2 = s.s2h, h2 = R(1) - R(0.5) * s2;
   const R h3 = R(1) - R(0.5) * s3, h4 = R(1) - R(0.5) * s4;
   m1 = m1 + s.Fx;
   m2 = m2 + s.Fy;
-  m3 = m3 - s2 * (m3 - (s.P + Ax * ux)) + h2 * (B * third + mxx);
-  m4 = m4 - s2 * (m4 - (s.P + Ay * uy)) + h2 * (B * third + myy);
+  m3 = m3 - s2 * (m3 - (s.P + Ax * ux)) + h2 * (third_of(B) + mxx);
+  m4 = m4 - s2 * (m4 - (s.P + Ay * uy)) + h2 * (third_of(B) + myy);
   m5 = m5 - s2 * (m5 - R(0.5) * (Ax * uy + Ay * ux)) + h2 * mxy;
-  m6 = m6 - s3 * (m6 - s.jx * third) + h3 * (s.Fx * third);
-  m7 = m7 - s3 * (m7 - s.jy * third) + h3 * (s.Fy * third);
-  m8 = m8 - s4 * (m8 - third * (s.P + Au)) + h4 * (B * ninth + third * (mxx + myy));
+  m6 = m6 - s3 * (m6 - third_of(s.jx)) + h3 * third_of(s.Fx);
+  m7 = m7 - s3 * (m7 - third_of(s.jy)) + h3 * third_of(s.Fy);
+  m8 = m8 - s4 * (m8 - third_of(s.P + Au)) + h4 * (ninth_of(B) + third_of(mxx + myy));
   h[0] = R(0.5) * (m1 + m3 - m6 - m8);
   h[1] = R(0.5) * (m2 + m4 - m7 - m8);
   h[2] = R(0.5) * (-m1 + m3 + m6 - m8);

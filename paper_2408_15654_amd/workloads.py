@@ -345,10 +345,12 @@ def e1_surface_diffusion(nx=100, R=25.0, steps=200) -> Problem:
 
 
 def random_small(seed: int, nx=None, ny=None, walls=None, r=None, eos=None,
-                 precision="fp64", steps=20) -> Problem:
+                 precision="fp64", steps=20, wall_drop=False) -> Problem:
     """Random small problem for parity tests: odd sizes, walls or periodic,
     r in {0,1,2}, linear or Langmuir EOS, density/viscosity ratios, random
-    drop and velocity field."""
+    drop and velocity field.  wall_drop (with walls): the drop is centred on
+    the bottom wall and fluid A is 3 or 10 times denser than fluid B, so
+    the dense fluid lies against a moving wall."""
     rng = np.random.default_rng(SEED_BASE + 1000 + seed)
     nx = int(rng.integers(40, 130)) if nx is None else nx
     ny = int(rng.integers(20, 70)) if ny is None else ny
@@ -356,6 +358,8 @@ def random_small(seed: int, nx=None, ny=None, walls=None, r=None, eos=None,
     r = float(rng.choice([0.0, 1.0, 2.0])) if r is None else r
     eos = str(rng.choice(["linear", "langmuir"])) if eos is None else eos
     rhoA = float(rng.choice([1.0, 3.0, 10.0]))
+    if wall_drop:
+        rhoA = float(rng.choice([3.0, 10.0]))
     muA = float(rng.uniform(0.05, 0.3))
     U = 0.02 if walls else 0.0
     p = base_params(nx, ny, walls_y=int(walls), u_wall_bot=-U * rng.uniform(0, 1),
@@ -368,8 +372,13 @@ def random_small(seed: int, nx=None, ny=None, walls=None, r=None, eos=None,
                     s_free=rng.uniform(0.8, 1.6, size=(3, 3)).tolist(),
                     precision=precision)
     R = min(nx, ny) * float(rng.uniform(0.2, 0.3))
-    phi, th = single_drop(nx, ny, R, cx=nx * rng.uniform(0.4, 0.6),
-                          cy=(ny - 1) * rng.uniform(0.45, 0.55), W=4.0,
+    cy = (ny - 1) * rng.uniform(0.45, 0.55)
+    if wall_drop:
+        if not walls:
+            raise ValueError("wall_drop needs walls")
+        R = min(nx, 2 * ny) * 0.3
+        cy = 0.0
+    phi, th = single_drop(nx, ny, R, cx=nx * rng.uniform(0.4, 0.6), cy=cy, W=4.0,
                           periodic_y=not walls)
     psi = float(rng.uniform(0.3, 0.6)) * (1 + 0.4 * np.cos(th + rng.uniform(0, 6))) * unit_peak(phi)
     x, y = _grid(nx, ny)
