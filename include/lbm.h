@@ -24,8 +24,13 @@
  *          the device; lbm_read_fields, lbm_moments and lbm_get_state
  *          synchronise the stream.
  * Errors   Every call returns an lbm_status; no C++ exception crosses the
- *          ABI.  A call that fails leaves the simulation as it was;
- *          lbm_last_error gives a message.  A non-finite value produced on
+ *          ABI.  A call that fails before it changes device state leaves
+ *          the simulation as it was; one that fails after (a HIP error
+ *          while lbm_init_fields or lbm_set_state overwrite the state, or
+ *          a launch failure after lbm_step has enqueued some steps) leaves
+ *          no valid state, and lbm_step returns LBM_ESTATE until
+ *          lbm_init_fields or lbm_set_state succeed.  lbm_last_error gives
+ *          a message.  A non-finite value produced on
  *          the device raises a sticky device flag that the next
  *          synchronising call reports as LBM_ENONFINITE; after that,
  *          lbm_step returns LBM_ESTATE until lbm_init_fields or
@@ -160,7 +165,10 @@ lbm_status lbm_step(lbm_handle *h, int64_t nsteps);
 lbm_status lbm_read_fields(lbm_handle *h, double *phi, double *psi, double *ux,
                            double *uy, double *P);
 
-/* Float64 domain sums of the current time level (deterministic order).
+/* Float64 domain sums of the current time level (deterministic order):
+ * the conserved totals of the phase field (sum of phi, Eq. (24)) and of
+ * the surfactant (sum of psi, Eq. (27)), the momentum and kinetic energy of
+ * the velocity of Eq. (32a) with rho(phi) of Eq. (15), and max |u|.
  * Synchronises the stream.  Errors: LBM_EINVAL (NULL out), LBM_ESTATE,
  * LBM_ENONFINITE, LBM_EDEVICE. */
 lbm_status lbm_moments(lbm_handle *h, lbm_moments_t *out);
@@ -198,7 +206,9 @@ size_t lbm_state_bytes(const lbm_handle *h);
 lbm_status lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes);
 lbm_status lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
 
-/* Release the handle (not the caller's workspace).  NULL is ignored. */
+/* Release the handle (not the caller's workspace), after waiting for the
+ * work it enqueued on its stream, so the workspace may be freed or reused
+ * as soon as this returns.  NULL is ignored. */
 void lbm_destroy(lbm_handle *h);
 
 /* Message of the last failed call on h (or of the last failed lbm_create

@@ -1968,7 +1968,7 @@ const char *validate(const lbm_params *p) {
     const double s = p->fp16_scale[a];
     if (s == 0) continue;
     int e;
-    if (!(s > 0) || std::frexp(s, &e) != 0.5 || e < -30 || e > 31)
+    if (!(s > 0) || std::frexp(s, &e) != 0.5 || e < -29 || e > 31)  // s = 2^(e-1)
       return "fp16_scale entries must be 0 or powers of two in [2^-30, 2^30]";
   }
   return nullptr;
@@ -2296,8 +2296,10 @@ int query_waves_resident(lbm_handle *h) {
 }
 
 template <class P>
-hipError_t launch_macros(lbm_handle *h) {
+hipError_t launch_macros(lbm_handle *h, double *sc, long long plane) {
   SiteArgs<P> a = site_args<P>(h);
+  a.scratch = sc;
+  a.plane = plane;
   const long long n = (long long)h->p.nx * h->p.ny;
   const int blocks = int((n + 255) / 256);
   const Phys<typename P::R> p = make_phys<typename P::R>(h->p);
@@ -2312,13 +2314,16 @@ hipError_t launch_macros(lbm_handle *h) {
   return hipGetLastError();
 }
 
-hipError_t run_macros(lbm_handle *h) {
+// The macroscopic fields of the current level into kScratch float64 planes
+// of `plane` elements at sc (default: the handle's own scratch).
+hipError_t run_macros(lbm_handle *h, double *sc, long long plane) {
   switch (h->p.precision) {
-    case LBM_FP64: return launch_macros<F64>(h);
-    case LBM_FP32: return launch_macros<F32>(h);
-    default: return launch_macros<F16>(h);
+    case LBM_FP64: return launch_macros<F64>(h, sc, plane);
+    case LBM_FP32: return launch_macros<F32>(h, sc, plane);
+    default: return launch_macros<F16>(h, sc, plane);
   }
 }
+hipError_t run_macros(lbm_handle *h) { return run_macros(h, scratch(h), h->L.plane); }
 
 template <class P>
 hipError_t launch_init(lbm_handle *h) {
@@ -2412,6 +2417,9 @@ lbm_status lbm_init_fields(lbm_handle *h, const double *phi, const double *psi,
                                   hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) return hip_check(h, e, "copying initial fields");
   }
+  // from here on the stored state is being replaced: a failure leaves no
+  // valid state (LBM_ESTATE until a later init or set_state succeeds)
+  h->valid = false;
   h->cur = 0;
   hipError_t e = run_init(h);
   if (e == hipSuccess) e = hipMemsetAsync(flagp(h), 0, sizeof(int), h->stream);
@@ -2428,7 +2436,12 @@ lbm_status lbm_step(lbm_handle *h, int64_t nsteps) {
   if (!h->valid) return fail(h, LBM_ESTATE, "no valid state");
   for (int64_t t = 0; t < nsteps; ++t) {
     hipError_t e = run_step(h);
-    if (e != hipSuccess) return hip_check(h, e, "launching the step kernel");
+    if (e != hipSuccess) {
+      // the launches already enqueued still run: the state is no longer the
+      // one before the call, nor a known number of steps past it
+      if (t > 0) h->valid = false;
+      return hip_check(h, e, "launching the step kernel");
+    }
     h->cur ^= 1;
     h->step += 1;
   }
@@ -2582,6 +2595,9 @@ lbm_status lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
   int64_t step;
   std::memcpy(&step, b, sizeof(int64_t));
   b += sizeof(int64_t);
+  // the stored state is overwritten from here on: a failure leaves no valid
+  // state (LBM_ESTATE until a later init or set_state succeeds)
+  h->valid = false;
   h->cur = 0;
   void *parts[3] = {pops(h, 0), rest(h, 0), auxp(h)};
   const size_t sizes[3] = {h->L.pop_bytes, h->L.rest_bytes, h->L.aux_bytes};
@@ -2598,7 +2614,13 @@ lbm_status lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
   return LBM_OK;
 }
 
-void lbm_destroy(lbm_handle *h) { delete h; }
+void lbm_destroy(lbm_handle *h) {
+  if (!h) return;
+  // work enqueued by lbm_step may still be writing the caller's workspace;
+  // finish it before the caller can release or reuse that memory
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
 
 const char *lbm_last_error(const lbm_handle *h) {
   return h ? h->err.c_str() : g_create_error.c_str();

@@ -50,7 +50,9 @@ def test_workspace_bytes_and_validation_without_device():
         assert n >= 64 * 64 * per_site
     bad = [dict(nx=2), dict(W=0.0), dict(M=-1.0), dict(D=0.0), dict(r=-0.5),
            dict(rhoA=0.0), dict(muB=-1.0), dict(phiA=0.0, phiB=0.0),
-           dict(s_free=[[2.5, 1, 1], [1, 1, 1], [1, 1, 1]]), dict(sigma0=-1.0)]
+           dict(s_free=[[2.5, 1, 1], [1, 1, 1], [1, 1, 1]]), dict(sigma0=-1.0),
+           dict(fp16_scale=(2.0 ** -31, 0, 0)), dict(fp16_scale=(0, 2.0 ** 31, 0)),
+           dict(fp16_scale=(0, 0, 3.0))]
     for kw in bad:
         c = lbm.to_c_params(dict(pr.params, **kw))
         assert lib.lbm_workspace_bytes(ctypes.byref(c)) == 0, kw
@@ -60,6 +62,9 @@ def test_workspace_bytes_and_validation_without_device():
         assert st == lbm.LBM_EINVAL, kw
         assert h.value is None
         assert lib.lbm_last_error(None)
+    for ok in ((2.0 ** -30, 2.0 ** 30, 1.0), (0, 4096.0, 0)):
+        c = lbm.to_c_params(dict(pr.params, precision="fp16dev", fp16_scale=ok))
+        assert lib.lbm_workspace_bytes(ctypes.byref(c)) > 0, ok
     # too-small workspace
     c = lbm.to_c_params(pr.params)
     h = ctypes.c_void_p()
