@@ -173,6 +173,28 @@ lbm_status lbm_read_fields(lbm_handle *h, double *phi, double *psi, double *ux,
  * LBM_ENONFINITE, LBM_EDEVICE. */
 lbm_status lbm_moments(lbm_handle *h, lbm_moments_t *out);
 
+/* For callers that cannot allocate device memory or wait for the device:
+ * code under HIP graph capture and tight serving loops.  The float64 sums
+ * of lbm_moments, enqueued on the handle's stream and written to device
+ * memory, with no allocation, no host transfer and no synchronisation:
+ *   dev_out[0..6] = sum phi, sum psi, mom_x, mom_y, kinetic, max |u|,
+ *                   non-finite (1.0 if phi, psi or u is not finite, else 0.0)
+ * in the order and with the values lbm_moments gives (the same kernels).
+ * dev_out: device memory on the handle's device for 7 doubles, owned by
+ * the caller; it holds the results once the stream reaches this point.
+ * The read-back planes and partial sums live in a static buffer the
+ * library holds on each device (32.1 MiB, for grids of up to 524288 =
+ * 2^19 sites), not in the handle's workspace; every call on one device
+ * shares it, so calls that may overlap on one device (different streams,
+ * different threads) race and must be ordered by the caller.  Nothing in
+ * it needs clearing: each call writes all it reads.  The sticky
+ * non-finite flag of the step is not read (that would synchronise); use
+ * dev_out[6], or the next synchronising call.
+ * Errors: LBM_EINVAL (NULL dev_out, more than 524288 sites), LBM_ESTATE
+ * (no valid state), LBM_EDEVICE (launch failure, or no address of the
+ * static buffer on this device). */
+lbm_status lbm_moments_async(lbm_handle *h, double *dev_out);
+
 /* Shape of fluid A at the current time level, float64, from the phase
  * field phi (c = (phi - phi_B)/(phi_A - phi_B) is the fluid-A fraction):
  * the quantities the paper follows for a sheared drop (interface length,

@@ -42,6 +42,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -2056,6 +2057,7 @@ struct lbm_handle {
   int waves_resident;  // step wavefronts the device holds at once (0: unknown)
   std::string kernel;  // the step kernel variant, as a profiler names it
   std::string err;
+  double *fixed_scratch;  // this device's copy of the static read-back scratch
 };
 
 // Step launches: compiled in both passes of this file (see lbm_f16_part).
@@ -2325,6 +2327,40 @@ hipError_t run_macros(lbm_handle *h, double *sc, long long plane) {
 }
 hipError_t run_macros(lbm_handle *h) { return run_macros(h, scratch(h), h->L.plane); }
 
+// Read-back scratch of lbm_moments_async in static device memory, for
+// callers that cannot allocate: kScratch float64 planes of at most
+// kFixedSites sites, then the reduction partials.  Each device holds its own
+// copy for the life of the process (32.1 MiB); host code reaches it only
+// through the address hipGetSymbolAddress gives for that device.
+constexpr long long kFixedSites = 1LL << 19;
+constexpr long long kFixedDoubles = kScratch * kFixedSites + kReduceBlocks * kReduceVals;
+static __device__ __align__(256) double fixed_scratch[kFixedDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+double *g_fixed_ptr[kMaxDevices];  // per device, resolved once
+
+// This device's address of fixed_scratch (nullptr if it cannot be had),
+// resolved once per device with that device current.
+double *fixed_scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_fixed_mu);
+  if (!g_fixed_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(fixed_scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_fixed_ptr[dev] = static_cast<double *>(ptr);
+  }
+  return g_fixed_ptr[dev];
+}
+
 template <class P>
 hipError_t launch_init(lbm_handle *h) {
   SiteArgs<P> a = site_args<P>(h);
@@ -2393,6 +2429,10 @@ lbm_status lbm_create(const lbm_params *params, void *dev_ws, size_t ws_bytes,
   h->waves_resident = query_waves_resident(h);
   h->rows = single_rows(h);
   h->kernel = kernel_name_of(h);
+  int dev = -1;
+  h->fixed_scratch = hipStreamGetDevice(h->stream, &dev) == hipSuccess ? fixed_scratch_of(dev)
+                                                                      : nullptr;
+  (void)hipGetLastError();
   *out = h;
   return LBM_OK;
 }
@@ -2504,6 +2544,28 @@ lbm_status lbm_moments(lbm_handle *h, lbm_moments_t *out) {
     return fail(h, LBM_ENONFINITE, "non-finite macroscopic field");
   }
   return LBM_OK;
+}
+
+lbm_status lbm_moments_async(lbm_handle *h, double *dev_out) {
+  if (!h) return LBM_EINVAL;
+  if (!dev_out) return fail(h, LBM_EINVAL, "dev_out is NULL");
+  if (!h->valid) return fail(h, LBM_ESTATE, "no valid state");
+  const long long n = (long long)h->p.nx * h->p.ny;
+  if (n > kFixedSites)
+    return fail(h, LBM_EINVAL, "grid has more than 524288 sites, the capacity of the static "
+                               "read-back scratch of lbm_moments_async (use lbm_moments)");
+  double *base = h->fixed_scratch;
+  if (!base) return fail(h, LBM_EDEVICE, "no address of the static read-back scratch");
+  const long long plane = (long long)align_up((size_t)n, 64);
+  hipError_t e = run_macros(h, base, plane);
+  if (e != hipSuccess) return hip_check(h, e, "launching read-back kernels");
+  double *part = base + kScratch * kFixedSites;
+  const Phys<double> p = make_phys<double>(h->p);
+  hipLaunchKernelGGL(lbm_reduce_kernel, dim3(kReduceBlocks), dim3(256), 0, h->stream,
+                     (const double *)base, plane, n, p, part);
+  hipLaunchKernelGGL(lbm_reduce_final_kernel, dim3(1), dim3(64), 0, h->stream,
+                     (const double *)part, kReduceBlocks, dev_out);
+  return hip_check(h, hipGetLastError(), "launching the reductions");
 }
 
 lbm_status lbm_shape(lbm_handle *h, lbm_shape_t *out) {

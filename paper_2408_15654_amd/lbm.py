@@ -67,7 +67,8 @@ class lbm_schedule(ctypes.Structure):
 
 
 EXPORTS = ("lbm_workspace_bytes", "lbm_create", "lbm_init_fields", "lbm_step",
-           "lbm_read_fields", "lbm_moments", "lbm_state_bytes", "lbm_get_state",
+           "lbm_read_fields", "lbm_moments", "lbm_moments_async", "lbm_state_bytes",
+           "lbm_get_state",
            "lbm_set_state", "lbm_destroy", "lbm_last_error", "lbm_set_tile_rows",
            "lbm_step_kernel_name")
 
@@ -98,6 +99,7 @@ def load(path: str = LIB_PATH):
     lib.lbm_step.argtypes = [H, ctypes.c_int64]
     lib.lbm_read_fields.argtypes = [H, dp, dp, dp, dp, dp]
     lib.lbm_moments.argtypes = [H, ctypes.POINTER(lbm_moments_t)]
+    lib.lbm_moments_async.argtypes = [H, vp]
     lib.lbm_state_bytes.argtypes = [H]
     lib.lbm_state_bytes.restype = ctypes.c_size_t
     lib.lbm_get_state.argtypes = [H, vp, ctypes.c_size_t]
@@ -110,7 +112,8 @@ def load(path: str = LIB_PATH):
     lib.lbm_step_kernel_name.argtypes = [H]
     lib.lbm_step_kernel_name.restype = ctypes.c_char_p
     for name in ("lbm_create", "lbm_init_fields", "lbm_step", "lbm_read_fields",
-                 "lbm_moments", "lbm_get_state", "lbm_set_state", "lbm_set_tile_rows"):
+                 "lbm_moments", "lbm_moments_async", "lbm_get_state", "lbm_set_state",
+                 "lbm_set_tile_rows"):
         getattr(lib, name).restype = ctypes.c_int
     # batches
     B, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -240,6 +243,21 @@ class Simulation:
         m = lbm_moments_t()
         self._check(self.lib.lbm_moments(self._handle, ctypes.byref(m)))
         return {k: getattr(m, k) for k, _ in lbm_moments_t._fields_ if k != "pad"}
+
+    MOMENTS_ASYNC = ("sum_phi", "sum_psi", "mom_x", "mom_y", "kinetic", "max_u", "nonfinite")
+
+    def moments_async(self, out):
+        """lbm_moments_async: the float64 sums, in the order of
+        MOMENTS_ASYNC, written to the float64 device tensor `out` (7 or more
+        elements, on this simulation's device) on the simulation's stream;
+        nothing is allocated and nothing waits."""
+        import torch
+
+        if (not isinstance(out, torch.Tensor) or out.dtype != torch.float64
+                or out.device != self.device or out.numel() < 7 or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 tensor of >= 7 elements "
+                             "on the simulation's device")
+        self._check(self.lib.lbm_moments_async(self._handle, ctypes.c_void_p(out.data_ptr())))
 
     def shape(self) -> dict:
         """Shape diagnostics of fluid A (area, centroid, moments, interface
