@@ -29,15 +29,15 @@ KERNEL_SOURCES = ("paper_2408_15654_amd/csrc/lbm.hip", "paper_2408_15654_amd/csr
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "lbm_step_kernel_many_drops_2048_{}_counters.txt")
 
 
-def algorithmic_bytes_per_site(precision: str, has_s: bool) -> int:
+def algorithmic_bytes_per_site(precision: str) -> int:
     """Bytes one site-update must move: 26 live populations read and written
     (f_0..f_8, g_0..g_8, h_1..h_8) plus the previous level read and written.
-    float64/float32 storage keep (phi, psi) as rest values and (ux, uy) and,
-    with a density contrast, (Sx, Sy) as aux; float16 storage keeps
-    (phi, psi, P, rho ux, rho uy) in float32 as rest values (the bases of the
-    stored deviations) and (Sx, Sy) as aux."""
-    s = 2 if has_s else 0
-    fields = 5 + s if precision == "fp16dev" else 4 + s
+    float64/float32 storage keep (phi, psi) as rest values and (ux, uy) as
+    aux; float16 storage keeps (phi, psi, P, rho ux, rho uy) in float32 as
+    rest values (the bases of the stored deviations, and rho u / rho(phi) is
+    the previous velocity).  The previous level's mass flux S is recomputed
+    from the previous phi, which the step reads anyway."""
+    fields = 5 if precision == "fp16dev" else 4
     return 2 * 26 * STORE_BYTES[precision] + 2 * fields * FIELD_BYTES[precision]
 
 
@@ -461,8 +461,7 @@ def main():
     sites = pr.sites
     sec = wall
     mlups = sites * args.steps / sec / 1e6
-    has_s = pr.params["rhoA"] != pr.params["rhoB"]
-    bps = algorithmic_bytes_per_site(args.precision, has_s)
+    bps = algorithmic_bytes_per_site(args.precision)
     per_launch_ms = ms_events / args.steps
     achieved = bps * sites / (per_launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(sites, args.precision)

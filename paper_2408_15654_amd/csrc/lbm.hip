@@ -99,8 +99,7 @@ struct F64 {
   static constexpr int kStorePol = kStoreNT;  // step kernel store cache policy
   static constexpr bool HDEV = false;  // h stored raw
   static constexpr int kRest = 2;      // rest record: phi, psi
-  static constexpr int kAux = 4;       // aux record: ux, uy, Sx, Sy
-  static constexpr int kAuxS = 2;      // offset of Sx in the aux record
+  static constexpr int kAux = 2;       // aux record: ux, uy
 };
 struct F32 {
   using S = float;
@@ -112,8 +111,7 @@ struct F32 {
   static constexpr int kStorePol = kStoreNT;  // step kernel store cache policy
   static constexpr bool HDEV = false;
   static constexpr int kRest = 2;
-  static constexpr int kAux = 4;
-  static constexpr int kAuxS = 2;
+  static constexpr int kAux = 2;
 };
 struct F16 {
   using S = _Float16;
@@ -127,11 +125,11 @@ struct F16 {
   static constexpr int kStorePol = kStoreDefault;  // step kernel store cache policy
   // h_k stored as deviations from 3 w_k (P + c_k . rho u) of the storing
   // site; P and rho u join phi, psi in the rest record, and the previous
-  // velocity is rho u / rho(phi) of that record, so aux holds S only.
+  // velocity is rho u / rho(phi) of that record, so the Navier-Stokes step
+  // reads no aux record (it holds only a prescribed velocity).
   static constexpr bool HDEV = true;
   static constexpr int kRest = 5;  // rest record: phi, psi, P, rho ux, rho uy
-  static constexpr int kAux = 2;   // aux record: Sx, Sy
-  static constexpr int kAuxS = 0;
+  static constexpr int kAux = 2;   // aux record: ux, uy (prescribed flow only)
 };
 // The same storage with default stores: what one step writes is then read
 // by the next one from the Infinity Cache while the simulation fits it.
@@ -1014,8 +1012,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   const rsrc_t raux = make_rsrc(a.aux, unsigned(P::kAux) * nsites * EA);
   const Phys<R> &p = a.p;
   const Scales<P> &sc = a.sc;
-  // float32 aux records read and written whole (one guarded 16-byte access)
-  constexpr bool kAuxQuad = sizeof(A) == 4 && P::kAux == 4 && HAS_S && NS;
+  // the aux records (ux, uy) of a lane's two float32 sites: one 16-byte access
+  constexpr bool kAuxQuad = sizeof(A) == 4 && K == 2;
+  // the step reads an aux record: the previous velocity, or the prescribed one
+  constexpr bool kAuxRead = !P::HDEV || !NS;
 
   // old (phi, psi) of this lane's columns at row y, wrapped or clamped
   auto rest_at = [&](int y, R *X, R *Y) {
@@ -1041,7 +1041,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       Pull2<P>::fg(rsrc, nxb, o, co.p0, d, q);
   };
   // loads of row y that the rebuild of row y+1 does not need
-  auto load_row = [&](int y, R (*h)[8], R *uxp, R *uyp, R *Sxp, R *Syp) {
+  auto load_row = [&](int y, R (*h)[8], R *uxp, R *uyp) {
     if constexpr (NS) {
       const RowOff o = row_offsets(y, ny, walls, rows_s);
       if constexpr (K == 1)
@@ -1049,27 +1049,20 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       else
         Pull2<P>::h(rsrc, hb, nxh, o, co.h0, h);
     }
+    // u: the previous level, or the prescribed field; with float16 storage
+    // the previous velocity comes from the rest record (P, rho u) instead
+    if constexpr (!kAuxRead) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const unsigned bk = baux + unsigned(k) * P::kAux * EA;
-      if constexpr (kAuxQuad) {  // (ux, uy, Sx, Sy) in one access
-        QuadIO::load(raux, bk, unsigned(y) * arow, uxp[k], uyp[k], Sxp[k], Syp[k]);
-      } else {
+      for (int k = 0; k < K; ++k) uxp[k] = uyp[k] = R(0);
+    } else if constexpr (kAuxQuad) {  // (ux, uy) of both sites in one access
+      QuadIO::load(raux, baux, unsigned(y) * arow, uxp[0], uyp[0], uxp[1], uyp[1]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
         A u, v;
-        if constexpr (!P::HDEV || !NS) {  // u: previous level, or the prescribed field
-          PairIO<A>::load(raux, bk, unsigned(y) * arow, u, v);
-          uxp[k] = R(u);
-          uyp[k] = R(v);
-        } else {  // from the rest record (P, rho u) instead
-          uxp[k] = uyp[k] = R(0);
-        }
-        if (HAS_S && NS) {
-          PairIO<A>::load(raux, bk + P::kAuxS * EA, unsigned(y) * arow, u, v);
-          Sxp[k] = R(u);
-          Syp[k] = R(v);
-        } else {
-          Sxp[k] = Syp[k] = R(0);
-        }
+        PairIO<A>::load(raux, baux + unsigned(k) * P::kAux * EA, unsigned(y) * arow, u, v);
+        uxp[k] = R(u);
+        uyp[k] = R(v);
       }
     }
   };
@@ -1163,12 +1156,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   // covers the loads it needs, not the stores just issued.
   R dn[K][9], qn[K][9];  // raw deviations of row y+1
   R hr[K][8];            // h of row y
-  R uxr[K], uyr[K], Sxr[K], Syr[K];
+  R uxr[K], uyr[K];
   // above the top wall the next row is the mirror ghost: the load of row
   // ny-1 keeps the sequence uniform and its values are not used
   auto next_fg_row = [&](int y) { return (walls && y >= ny) ? ny - 1 : wrap_y(y); };
   load_fg(next_fg_row(y0 + 1), dn, qn);
-  load_row(y0, hr, uxr, uyr, Sxr, Syr);
+  load_row(y0, hr, uxr, uyr);
   // rest (P, rho u) of rows y-1, y, y+1 and the prefetched y+2
   HR Hm{}, Hc{}, Hn{}, Hq{};
   if constexpr (P::HDEV && NS) {
@@ -1214,8 +1207,18 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     R uxp[K], uyp[K], Sxp[K], Syp[K];
     copy(uxp, uxr);
     copy(uyp, uyr);
-    copy(Sxp, Sxr);
-    copy(Syp, Syr);
+    // the previous level's mass flux, Eq. (16), from the previous phi of
+    // rows y-1, y, y+1 (the rest values the rebuilds read)
+    static_for<K>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      if constexpr (HAS_S && NS) {
+        R gx, gy;
+        grad9(window_k<K, k>(X0, X1, X2), gx, gy);
+        mass_flux(p, X1[k], gx, gy, Sxp[k], Syp[k]);
+      } else {
+        Sxp[k] = Syp[k] = R(0);
+      }
+    });
     if constexpr (P::HDEV && NS) {  // add back the rest parts of the arriving h
       // (no contraction: float16 storage rounds stochastically from all
       // 32 bits, so every copy of the row code must give the same bits)
@@ -1248,12 +1251,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     if constexpr (decltype(prefetch)::value) {
       rest_at(y + 3, X4, Y4);
       load_fg(next_fg_row(y + 2), dn, qn);
-      load_row(y + 1, hr, uxr, uyr, Sxr, Syr);
+      load_row(y + 1, hr, uxr, uyr);
       hrest_at(y + 2, Hq);
     }
 
     const bool bot = walls && y == 0, top = walls && y == ny - 1;
-    R oux[K], ouy[K], oSx[K], oSy[K];
+    R oux[K], ouy[K];
     HR hn{};
     static_for<K>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
@@ -1296,8 +1299,6 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       }
       oux[k] = s.ux;
       ouy[k] = s.uy;
-      oSx[k] = s.Sx;
-      oSy[k] = s.Sy;
       bad |= interior && !isfinite(phc[k] + psc[k] + s.ux + s.uy);
     });
 
@@ -1340,18 +1341,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
         PairIO<A>::template store<P::kStorePol>(A(lp(phc[0])), A(lp(psc[0])), rdrest, brest_s,
                                                 unsigned(y) * rrow);
       }
-      if constexpr (kAuxQuad) {
-        QuadIO::store<P::kStorePol>(lp(oux[0]), lp(ouy[0]), lp(oSx[0]), lp(oSy[0]), raux,
-                                    baux_s, unsigned(y) * arow);
-      } else {
-        if constexpr (!P::HDEV && NS)
-          PairIO<A>::template store<P::kStorePol>(
-              A(lp(oux[0])), A(lp(ouy[0])), raux, baux_s, unsigned(y) * arow);
-        if (HAS_S && NS)
-          PairIO<A>::template store<P::kStorePol>(
-              A(lp(oSx[0])), A(lp(oSy[0])), raux, baux_s + P::kAuxS * EA,
-                           unsigned(y) * arow);
-      }
+      if constexpr (!P::HDEV && NS)
+        PairIO<A>::template store<P::kStorePol>(A(lp(oux[0])), A(lp(ouy[0])), raux, baux_s,
+                                                unsigned(y) * arow);
     } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
       for (int i = 0; i < 9; ++i)
@@ -1365,18 +1357,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       }
       QuadIO::store<P::kStorePol>(lp(phc[0]), lp(psc[0]), lp(phc[1]), lp(psc[1]), rdrest,
                                   brest_s, unsigned(y) * rrow);
-      if constexpr (NS) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const unsigned bk = baux_s + unsigned(k) * P::kAux * EA;
-          if constexpr (HAS_S)
-            QuadIO::store<P::kStorePol>(lp(oux[k]), lp(ouy[k]), lp(oSx[k]), lp(oSy[k]), raux,
-                                        bk, unsigned(y) * arow);
-          else
-            PairIO<A>::template store<P::kStorePol>(
-                lp(oux[k]), lp(ouy[k]), raux, bk, unsigned(y) * arow);
-        }
-      }
+      if constexpr (NS)
+        QuadIO::store<P::kStorePol>(lp(oux[0]), lp(ouy[0]), lp(oux[1]), lp(ouy[1]), raux,
+                                    baux_s, unsigned(y) * arow);
     } else {  // float16 deviations, scaled: four halves per (f, g) plane, two per h plane
       const unsigned site = unsigned(y) * unsigned(nx) + xc;
       unsigned w0[9], w1[9];
@@ -1406,9 +1389,6 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
                                     brest_s + 4 * EA, unsigned(y) * rrow);
         PairIO<A>::template store<P::kStorePol>(lp(hn.jx[1]), lp(hn.jy[1]), rdrest,
                                                 brest_s + 8 * EA, unsigned(y) * rrow);
-        if constexpr (HAS_S)
-          QuadIO::store<P::kStorePol>(lp(oSx[0]), lp(oSy[0]), lp(oSx[1]), lp(oSy[1]), raux,
-                                      baux_s + P::kAuxS * EA, unsigned(y) * arow);
       } else {
 #pragma unroll
         for (int k = 0; k < K; ++k)
@@ -1662,8 +1642,6 @@ lbm_init_kernel(const SiteArgs<P> a, const Phys<double> p) {
     a.aux[aux_idx<P>(0, y, x, nx)] = A(ux);
     a.aux[aux_idx<P>(1, y, x, nx)] = A(uy);
   }
-  a.aux[aux_idx<P>(P::kAuxS, y, x, nx)] = A(Sx);
-  a.aux[aux_idx<P>(P::kAuxS + 1, y, x, nx)] = A(Sy);
 }
 
 // Read-back, pass 1: phi, psi, sigma of the current level into scratch
@@ -1730,8 +1708,17 @@ lbm_macro_fields_kernel(const SiteArgs<P> a, const Phys<typename P::R> p) {
     a.scratch[4 * pl + k] = 0.0;
     return;
   }
-  const R Sxp = HAS_S ? R(a.aux[aux_idx<P>(P::kAuxS, y, x, nx)]) : R(0);
-  const R Syp = HAS_S ? R(a.aux[aux_idx<P>(P::kAuxS + 1, y, x, nx)]) : R(0);
+  // the previous level's mass flux from the previous phi, as in the step
+  R Sxp = R(0), Syp = R(0);
+  if constexpr (HAS_S) {
+    const auto *rs = a.src_rest;
+    const Nine<R> vq = gather9<R>(
+        [&](int yy, int xx) { return R(rs[rest_idx<P>(0, yy, xx, nx)]); }, x, y, nx, a.ny,
+        a.walls);
+    R gqx, gqy;
+    grad9(vq, gqx, gqy);
+    mass_flux(p, php, gqx, gqy, Sxp, Syp);
+  }
   const RowN r = row_numbers(y, a.ny, a.walls);
   R h[8];
   pull_h<P>(a.src, r, x, xm, xp, nx, a.sc.hi, rho_of(p, php), p.uwb, p.uwt, h);
@@ -2076,16 +2063,18 @@ int *flagp(lbm_handle *h) { return reinterpret_cast<int *>(h->ws + h->L.off_flag
 int sites_per_lane(const lbm_params &p) {
   return p.precision != LBM_FP64 && p.nx % 2 == 0 ? 2 : 1;
 }
-// Whether one step's traffic (every population, rest and aux value read and
-// written once) lies where default stores beat non-temporal ones: measured
+// Whether a grid lies where default stores beat non-temporal ones: measured
 // for float32 and float64 storage on single grids from 256x128 to 2048^2,
-// the default is 6-25% faster from 64 MB to 320 MB (the written populations
-// are read back from the Infinity Cache) and equal or slower outside.
+// the default is 6-25% faster (the written populations are read back from
+// the Infinity Cache) from 250 k to 1.25 M sites with float32 storage and
+// from 125 k to 625 k sites with float64 storage (64-320 MB of step traffic
+// at the 256 and 512 bytes per site the step moved when those measurements
+// were taken), and equal or slower outside.
 bool cache_resident(const lbm_params &p) {
-  const double per_site = p.precision == LBM_FP64 ? 2.0 * (26 + 2 + 4) * 8
-                                                  : 2.0 * (26 * 4 + (2 + 4) * 4);
-  const double bytes = per_site * double(p.nx) * double(p.ny);
-  return p.precision != LBM_FP16DEV && bytes >= 64e6 && bytes <= 320e6;
+  const double sites = double(p.nx) * double(p.ny);
+  if (p.precision == LBM_FP32) return sites >= 250e3 && sites <= 1.25e6;
+  if (p.precision == LBM_FP64) return sites >= 125e3 && sites <= 625e3;
+  return false;
 }
 
 int strips_of(const lbm_params &p) {

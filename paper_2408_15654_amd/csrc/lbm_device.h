@@ -122,6 +122,31 @@ struct Front {
   R s2h;                  // viscous rate, Eq. (33)
 };
 
+// Interface normal n = grad phi / (|grad phi| + eps) and delta(phi) of
+// Eq. (8), from phi and its gradient.
+template <class R>
+__device__ __forceinline__ void normal_delta(const Phys<R>& p, R phi, R gfx, R gfy, R& nx,
+                                             R& ny, R& delta) {
+  const R gn = sqrt(gfx * gfx + gfy * gfy);
+  const R inv = R(1) / (gn + p.eps_n);
+  nx = gfx * inv;
+  ny = gfy * inv;
+  delta = p.c4W * ((p.phiA - phi) * (phi - p.phiB));
+}
+
+// Mass flux of Eq. (16), S = M (rhoA - rhoB)/(phiA - phiB) (grad phi -
+// delta n), from phi and its gradient.  The step recomputes the previous
+// level's S this way from the stored previous phi (the stencil over the
+// rest values it reads anyway) instead of storing it: the same arithmetic
+// on the same values as the step that produced that level.
+template <class R>
+__device__ __forceinline__ void mass_flux(const Phys<R>& p, R phi, R gfx, R gfy, R& Sx, R& Sy) {
+  R nx, ny, delta;
+  normal_delta(p, phi, gfx, gfy, nx, ny, delta);
+  Sx = p.Mdrho * (gfx - delta * nx);
+  Sy = p.Mdrho * (gfy - delta * ny);
+}
+
 // Forces, closures and time differences at one site, from the stencils
 // (grad phi, lap phi, grad sigma, grad psi), sigma, the post-stream h_1..h_8
 // and the previous level (phi, psi, u, S).  Eqs. (8), (15), (16), (18),
@@ -134,12 +159,8 @@ __device__ __forceinline__ void site_front(const Phys<R>& p, Front<R>& s, R phi,
   s.phi = phi;
   s.psi = psi;
   const R gn2 = gfx * gfx + gfy * gfy;
-  const R gn = sqrt(gn2);
-  const R inv = R(1) / (gn + p.eps_n);
-  s.nx = gfx * inv;
-  s.ny = gfy * inv;
+  normal_delta(p, phi, gfx, gfy, s.nx, s.ny, s.delta);
   const R qa = p.phiA - phi, qb = phi - p.phiB, qab = p.phiAB - phi - phi;
-  s.delta = p.c4W * (qa * qb);
   s.a = p.c4W * qab;
   // capillary force sigma mu_phi grad phi plus Marangoni force, Eq. (18)
   const R muphi = p.cbulk * (qa * qb * qab) - p.cW * lphi;
@@ -149,8 +170,7 @@ __device__ __forceinline__ void site_front(const Phys<R>& p, Front<R>& s, R phi,
   s.Fx = sig * muphi * gfx + p.cW * (gn2 * gsx - sdp * gfx) + rho * p.gx;
   s.Fy = sig * muphi * gfy + p.cW * (gn2 * gsy - sdp * gfy) + rho * p.gy;
   if (HAS_S) {
-    s.Sx = p.Mdrho * (gfx - s.delta * s.nx);
-    s.Sy = p.Mdrho * (gfy - s.delta * s.ny);
+    mass_flux(p, phi, gfx, gfy, s.Sx, s.Sy);
     s.grx = p.drho * gfx;
     s.gry = p.drho * gfy;
   } else {
@@ -328,13 +348,8 @@ __device__ __forceinline__ void site_front_prescribed(const Phys<R>& p, Front<R>
                                                       R php, R psp) {
   s.phi = phi;
   s.psi = psi;
-  const R gn = sqrt(gfx * gfx + gfy * gfy);
-  const R inv = R(1) / (gn + p.eps_n);
-  s.nx = gfx * inv;
-  s.ny = gfy * inv;
-  const R qa = p.phiA - phi, qb = phi - p.phiB, qab = p.phiAB - phi - phi;
-  s.delta = p.c4W * (qa * qb);
-  s.a = p.c4W * qab;
+  normal_delta(p, phi, gfx, gfy, s.nx, s.ny, s.delta);
+  s.a = p.c4W * (p.phiAB - phi - phi);
   s.ux = ux;
   s.uy = uy;
   s.dpux = phi * ux - php * ux;
