@@ -193,11 +193,17 @@ def batched_sweep(n=256, steps=400, seq_steps=20, precision="fp32", probe=8):
     b.close()
     del b
     torch.cuda.empty_cache()
+    bps = algorithmic_bytes_per_site(precision)
+    achieved = bps * tuned * 1e6 / 1e9  # GB/s at the tuned rate
     return {"instances": n, "sites": total_sites, "precision": precision,
             "one_at_a_time_MLUPS": round(seq, 1), "batched_untuned_MLUPS": round(untuned, 1),
             "batched_tuned_MLUPS": round(tuned, 1), "tuned_schedule": chosen,
             "speedup_vs_one_at_a_time": round(tuned / seq, 2),
-            "workspace_bytes": hbm, "timed_steps": steps, "one_at_a_time_steps": seq_steps}
+            "workspace_bytes": hbm, "timed_steps": steps, "one_at_a_time_steps": seq_steps,
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "bytes_per_site_update": bps,
+                         "basis": "algorithmic bytes x batched site updates / wall time"}}
 
 
 def rel_errors(got, want):
@@ -498,14 +504,20 @@ def main():
     if not args.no_extras:
         # the batched sweep (256 problems) and a short serving stream, so the
         # one line carries every figure of the metric
-        out["batched"] = batched_sweep(steps=400)
+        # the batched sweep at its full 10000 steps (untuned and tuned)
+        out["batched"] = batched_sweep(steps=10000)
         progress(f"batched sweep: {out['batched']['batched_tuned_MLUPS']} MLUPS")
-        runs = serving_bench(n=60, budgets_gb=(64,), precisions=("fp32",), max_steps=5000,
-                             quiet=True)
-        out["serving"] = runs[0]
-        out["latency_p50_s"] = runs[0]["latency_p50_s"]
-        out["latency_p99_s"] = runs[0]["latency_p99_s"]
-        progress(f"serving stream: p50 {runs[0]['latency_p50_s']} s, p99 {runs[0]['latency_p99_s']} s")
+        # the serving stream, 100 solves of up to 10000 steps: float32 with a
+        # small (2 GB) and a large (64 GB) HBM budget, float16 deviations
+        # with the large one
+        runs = serving_bench(n=100, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"),
+                             max_steps=10000, quiet=True)
+        main = [r for r in runs if r["precision"] == "fp32" and r["budget_GB"] == 64][0]
+        out["serving"] = main
+        out["serving_runs"] = runs
+        out["latency_p50_s"] = main["latency_p50_s"]
+        out["latency_p99_s"] = main["latency_p99_s"]
+        progress(f"serving stream: p50 {main['latency_p50_s']} s, p99 {main['latency_p99_s']} s")
         out["precision_2048_5000_steps"] = precision_run()
         progress("precision run done")
         out["shear_drop_20000_steps"] = shear_run()

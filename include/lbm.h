@@ -307,10 +307,14 @@ lbm_status lbm_batch_create(int32_t max_instances, void *dev_ws, size_t ws_bytes
 
 /* Admit one simulation: validate params as lbm_create does, take
  * lbm_batch_instance_bytes(params) from the workspace, set the initial
- * state from host float64 fields as lbm_init_fields does (synchronising),
- * and give it nsteps steps to run.  *id receives its id (>= 0).  ENOMEM:
- * no free id or not enough contiguous free workspace now (nothing is
- * changed; retry after a retire).  EINVAL: bad parameters or fields. */
+ * state from host float64 fields as lbm_init_fields does, and give it
+ * nsteps steps to run.  The copy and initialisation run on a stream of the
+ * batch's own, so simulations enqueued earlier on the caller's stream keep
+ * stepping meanwhile; the call returns once the new state is in place
+ * (it waits for that stream only) and the simulation joins the next
+ * lbm_batch_step.  *id receives its id (>= 0).  ENOMEM: no free id or not
+ * enough contiguous free workspace now (nothing is changed; retry after a
+ * retire).  EINVAL: bad parameters or fields. */
 lbm_status lbm_batch_submit(lbm_batch *b, const lbm_params *params, const double *phi,
                             const double *psi, const double *ux, const double *uy,
                             int64_t nsteps, int32_t *id);

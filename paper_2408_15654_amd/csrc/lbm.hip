@@ -2766,6 +2766,7 @@ void launch_batch_class(int c, int blocks, hipStream_t st, const void *desc,
 struct lbm_batch {
   hipStream_t stream = nullptr;   // the caller's stream: all work goes here
   hipStream_t capture = nullptr;  // library stream used only to record graphs
+  hipStream_t admit = nullptr;    // library stream for joiners' copies and init
   char *ws = nullptr;
   size_t ws_bytes = 0;
   int max_inst = 0;
@@ -3015,6 +3016,7 @@ lbm_status lbm_batch_create(int32_t max_instances, void *dev_ws, size_t ws_bytes
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void **>(&b->h_count), sizeof(int) * kClasses);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->admit, hipStreamNonBlocking);
   int dev = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess)
@@ -3046,8 +3048,15 @@ lbm_status lbm_batch_submit(lbm_batch *b, const lbm_params *params, const double
   size_t off;
   if (!b->arena.alloc(bytes, &off))
     return bfail(b, LBM_ENOMEM, "not enough contiguous free workspace");
+  // The new simulation's fields are copied in and initialised on the
+  // batch's admission stream, so the simulations already stepping on the
+  // caller's stream keep running meanwhile.  Its block of the workspace is
+  // free of device work: a retire releases a block only after the stream
+  // has finished every launch that used it.  It joins the launches of the
+  // next lbm_batch_step, which are enqueued after this call has waited for
+  // the initialisation to complete.
   lbm_handle *h = nullptr;
-  lbm_status st = lbm_create(params, b->ws + off, bytes, b->stream, &h);
+  lbm_status st = lbm_create(params, b->ws + off, bytes, b->admit, &h);
   if (st == LBM_OK) {
     st = lbm_init_fields(h, phi, psi, ux, uy);
     if (st != LBM_OK) {
@@ -3062,6 +3071,7 @@ lbm_status lbm_batch_submit(lbm_batch *b, const lbm_params *params, const double
     b->arena.release(off, bytes);
     return st;
   }
+  h->stream = b->stream;  // reads and steps from now on go to the caller's stream
   auto &in = b->inst[slot];
   in.h = h;
   in.off = off;
@@ -3247,6 +3257,7 @@ void lbm_batch_destroy(lbm_batch *b) {
   if (b->h_count) (void)hipHostFree(b->h_count);
   if (b->h_tiles) (void)hipHostFree(b->h_tiles);
   if (b->capture) (void)hipStreamDestroy(b->capture);
+  if (b->admit) (void)hipStreamDestroy(b->admit);
   delete b;
 }
 

@@ -113,23 +113,35 @@ class Server:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
+            # the next chunk of the running solves goes to the device first;
+            # admissions below then overlap with it (the library copies and
+            # initialises joiners on a stream of its own) and join the chunk
+            # after
+            stepping = bool(running)
+            if stepping:
+                self.batch.step(self.chunk)
             # admit in the chosen order while they fit the budget and the
             # site cap (a request that does not fit waits; others may still
             # be admitted)
+            joined = {}
             for req in admission_order(waiting, self.order):
-                if not within_site_cap(running_sites, _sites(req), len(running),
+                if not within_site_cap(running_sites + sum(_sites(r) for r, _ in joined.values()),
+                                       _sites(req), len(running) + len(joined),
                                        self.max_running_sites):
                     continue
                 sid = self.batch.try_submit(req.params, *req.fields0, req.steps)
                 if sid is None:
                     continue
                 waiting.remove(req)
-                running[sid] = (req, clock() - t0)
-                running_sites += _sites(req)
+                joined[sid] = (req, clock() - t0)
                 if on_admit:
                     on_admit(req, sid)
-            peak_running = max(peak_running, len(running))
-            if not running:
+            if not stepping:
+                if joined:  # start them at once
+                    running.update(joined)
+                    running_sites += sum(_sites(r) for r, _ in joined.values())
+                    peak_running = max(peak_running, len(running))
+                    continue
                 if pending:  # idle until the next arrival
                     delay = pending[0].arrival - (clock() - t0)
                     if delay > 0:
@@ -138,11 +150,13 @@ class Server:
                 if waiting:
                     raise RuntimeError("a request does not fit the empty batch")
                 break
-            self.batch.step(self.chunk)
             torch.cuda.current_stream().synchronize()
-            for sid, (req, adm) in list(running.items()):
-                if self.batch.remaining(sid) > 0:
-                    continue
+            finished = [sid for sid in running if self.batch.remaining(sid) == 0]
+            running.update(joined)
+            running_sites += sum(_sites(r) for r, _ in joined.values())
+            peak_running = max(peak_running, len(running))
+            for sid in finished:
+                req, adm = running[sid]
                 fields = self.batch.read_fields(sid) if req.rid in keep_fields else None
                 self.batch.retire(sid)
                 del running[sid]
