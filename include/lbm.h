@@ -52,7 +52,9 @@ typedef enum {
   LBM_EINVAL = -1,     /* invalid argument or parameter */
   LBM_ENOMEM = -2,     /* workspace too small */
   LBM_EDEVICE = -3,    /* HIP runtime error */
-  LBM_ENONFINITE = -4, /* the device produced a NaN or Inf */
+  LBM_ENONFINITE = -4, /* the device produced a NaN or Inf (or, with
+                          LBM_FP16DEV, a scaled deviation beyond the float16
+                          range, which would be stored saturated) */
   LBM_ESTATE = -5      /* no valid state (not initialised, or after ENONFINITE) */
 } lbm_status;
 

@@ -808,19 +808,26 @@ __device__ __forceinline__ unsigned halves_sr(float lo, float hi, unsigned key) 
 // are added to the rest population, which stays at the site and is rounded
 // to nearest.  The deviations of a site sum to zero, so the stored ones
 // change the mass by that one rounding only, not by nine random ones.
+// amax takes the largest magnitude packed: the conversion saturates at the
+// float16 maximum 65504 without a sign of it, so the caller flags larger
+// values (or NaN) as a lost state.
 __device__ __forceinline__ void pack_fg(const float *f, const float *g, float sf, float sg,
-                                        unsigned site, unsigned *w) {
+                                        unsigned site, unsigned *w, float &amax) {
 #pragma clang fp contract(off)
   float ef = 0.f, eg = 0.f;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const float vf = f[i] * sf, vg = g[i] * sg;
+    amax = fmaxf(amax, fmaxf(fabsf(vf), fabsf(vg)));
     w[i] = halves_sr(vf, vg, site * 32u + unsigned(i));
     ef += vf - half_lo(w[i]);
     eg += vg - half_hi(w[i]);
   }
-  w[0] = halves(f[0] * sf + ef, g[0] * sg + eg);
+  const float v0 = f[0] * sf + ef, u0 = g[0] * sg + eg;
+  amax = fmaxf(amax, fmaxf(fabsf(v0), fabsf(u0)));
+  w[0] = halves(v0, u0);
 }
+constexpr float kHalfMax = 65504.f;  // largest finite float16
 
 // Pull streaming with two adjacent columns per lane (float32 storage, or
 // scaled float16 deviations): each population is loaded at the lane's own
@@ -1303,10 +1310,11 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     });
 
     const unsigned rcs = unsigned(y) * rows_s;
+    float amax = 0.f;  // largest scaled deviation stored as float16
     if constexpr (K == 1) {
       if constexpr (P::SCALED) {  // float16: packed words, stochastic rounding
         unsigned w[9];
-        pack_fg(dc[0], qc[0], sc.f, sc.g, unsigned(y) * unsigned(nx) + xc, w);
+        pack_fg(dc[0], qc[0], sc.f, sc.g, unsigned(y) * unsigned(nx) + xc, w, amax);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
           __builtin_amdgcn_raw_buffer_store_b32(lane_pick<HL>(interior, w[i]), rdst, cs.p0,
@@ -1320,12 +1328,14 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       if constexpr (NS && P::SCALED) {
         const unsigned key = (unsigned(y) * unsigned(nx) + xc) * 32u + 16u;
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 8; ++i) {
+          const float v = h[0][i] * sc.h;
+          amax = fmaxf(amax, fabsf(v));
           __builtin_amdgcn_raw_buffer_store_b16(
-              (unsigned short)(lane_pick<HL>(interior,
-                                             halves_sr(h[0][i] * sc.h, 0.f, key + unsigned(i))) &
+              (unsigned short)(lane_pick<HL>(interior, halves_sr(v, 0.f, key + unsigned(i))) &
                                0xffffu),
               rdst, cs.h0, rcs + hb + unsigned(i) * nxh, P::kStorePol);
+        }
       } else if constexpr (NS) {
 #pragma unroll
         for (int i = 0; i < 8; ++i)
@@ -1363,8 +1373,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     } else {  // float16 deviations, scaled: four halves per (f, g) plane, two per h plane
       const unsigned site = unsigned(y) * unsigned(nx) + xc;
       unsigned w0[9], w1[9];
-      pack_fg(dc[0], qc[0], sc.f, sc.g, site, w0);
-      pack_fg(dc[1], qc[1], sc.f, sc.g, site + 1u, w1);
+      pack_fg(dc[0], qc[0], sc.f, sc.g, site, w0, amax);
+      pack_fg(dc[1], qc[1], sc.f, sc.g, site + 1u, w1, amax);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         u32x2 w;
@@ -1375,11 +1385,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       }
       if constexpr (NS) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 8; ++i) {
+          const float v0 = h[0][i] * sc.h, v1 = h[1][i] * sc.h;
+          amax = fmaxf(amax, fmaxf(fabsf(v0), fabsf(v1)));
           __builtin_amdgcn_raw_buffer_store_b32(
-              lane_pick<HL>(interior, halves_sr(h[0][i] * sc.h, h[1][i] * sc.h,
-                                                site * 32u + 16u + unsigned(i))),
+              lane_pick<HL>(interior, halves_sr(v0, v1, site * 32u + 16u + unsigned(i))),
               rdst, cs.h0, rcs + hb + unsigned(i) * nxh, P::kStorePol);
+        }
       }
       if constexpr (P::HDEV && NS) {
         // the two 5-float rest records (40 bytes) as 16 + 16 + 8 bytes
@@ -1397,6 +1409,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
                                                   unsigned(y) * rrow);
       }
     }
+
+    // a deviation beyond the float16 range was stored saturated: the state
+    // is lost, as with a non-finite value
+    if constexpr (P::SCALED) bad |= interior && !(amax <= kHalfMax);
 
     // slide the windows
     copy(phm, phc);

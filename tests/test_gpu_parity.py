@@ -349,6 +349,28 @@ def test_nonfinite_is_reported_and_blocks_stepping():
     assert np.isfinite(sim.moments()["sum_phi"])
 
 
+def test_float16_saturation_is_reported():
+    """float16-deviation storage with a scale far too large for the
+    deviations (2^30 on f): the conversion would store them saturated at
+    65504, and the step reports that as a lost state (LBM_ENONFINITE),
+    after which stepping is refused.  The default scales stay clean."""
+    pr = W.c1_stationary_drop()
+    sim = lbm.Simulation(dict(pr.params, precision="fp16dev", fp16_scale=(2.0 ** 30, 0, 0)))
+    sim.init_fields(*pr.fields0)
+    sim.step(2)
+    with pytest.raises(lbm.NonFiniteError):
+        sim.moments()
+    with pytest.raises(lbm.LbmError) as e:
+        sim.step(1)
+    assert e.value.status == lbm.LBM_ESTATE
+    sim.close()
+    ok = lbm.Simulation(dict(pr.params, precision="fp16dev"))
+    ok.init_fields(*pr.fields0)
+    ok.step(50)
+    assert ok.moments()["nonfinite"] == 0
+    ok.close()
+
+
 def test_invalid_arguments():
     pr = W.c1_stationary_drop()
     with pytest.raises(lbm.LbmError):
