@@ -349,6 +349,23 @@ def test_nonfinite_is_reported_and_blocks_stepping():
     assert np.isfinite(sim.moments()["sum_phi"])
 
 
+def test_close_waits_for_the_work_on_a_side_stream():
+    """A simulation on a stream of its own (default priority): lbm_step only
+    enqueues, and lbm_destroy waits for that stream, so once close() returns
+    the workspace is no longer written and may be released or reused."""
+    import torch
+
+    pr = W.c3_many_drops(precision="fp32", nx=512, ny=512, ndrops=10)
+    side = torch.cuda.Stream()
+    sim = lbm.Simulation(pr.params, stream=side)
+    sim.init_fields(*pr.fields0)
+    sim.step(400)
+    sim.close()
+    assert side.query()
+    del sim
+    torch.cuda.synchronize()
+
+
 def test_float16_saturation_is_reported():
     """float16-deviation storage with a scale far too large for the
     deviations (2^30 on f): the conversion would store them saturated at
