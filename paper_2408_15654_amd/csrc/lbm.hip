@@ -13,15 +13,17 @@
 //   rest         one record per site, (phi, psi) of the same time level:
 //                the bases of those deviations;
 // plus, updated in place (each site reads and writes only its own entry):
-//   aux          one record per site, (ux, uy, Sx, Sy) of the previous time
-//                level (the first-order time differences need them); with a
-//                prescribed velocity, u itself;
+//   aux          one record per site, (ux, uy) of the previous time level
+//                (the first-order time differences need it; the previous
+//                level's mass flux S is recomputed from the previous phi
+//                of the rest records); with a prescribed velocity, u itself;
 //   scratch      float64 planes (plane-major) for host transfers and
 //                read-back.
 // Storage: float64, float32, or float16 deviations with per-field
 // power-of-two scales; with float16 storage h is also stored as deviations,
 // from 3 w_k (P + c_k . rho u) of the writing site, the rest record carries
-// (phi, psi, P, rho ux, rho uy) in float32 and aux only (Sx, Sy).
+// (phi, psi, P, rho ux, rho uy) in float32, and the previous velocity is
+// rho u / rho(phi) of that record (aux holds only a prescribed velocity).
 //
 // One time step is ONE launch of lbm_step_kernel.  Each wavefront owns a
 // strip of columns, 60 with one column per lane or 124 with two (float32
@@ -289,8 +291,8 @@ __device__ __forceinline__ int wrap_row(int y, int ny, int walls) {
 //   block FG: for i = 0..8, nx pairs (f_i, g_i)      -> 18 nx values
 //   block H:  for i = 1..8, nx values h_i             ->  8 nx values
 // so f_i and g_i, which stream from the same source site, arrive in one
-// load.  The rest group holds (phi, psi) pairs and the aux group
-// (ux, uy, Sx, Sy) quadruples, one per site.
+// load.  The rest group holds (phi, psi) pairs and the aux group (ux, uy)
+// pairs, one per site.
 __device__ __forceinline__ long long fg_idx(int i, int c, int y, int x, int nx) {
   return (long long)y * (kPlanes * nx) + (long long)(i * nx + x) * 2 + c;
 }
