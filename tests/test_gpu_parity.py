@@ -126,6 +126,18 @@ def test_drop64_fp16dev_conserves_mass():
         assert abs(m[k] - mo[k]) <= 1e-6 * abs(mo[k]), (k, m[k], mo[k])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
+def test_surface_diffusion_run(precision):
+    """Surfactant diffusing along a circle at rest (Sec. 4.1 set-up in
+    lattice units: 100x100, R = 25, tau_psi = 9.875), its full 200 steps."""
+    pr = W.e1_surface_diffusion()
+    sim, got = run_gpu(pr, precision, pr.steps)
+    _, want = run_oracle(pr, pr.steps)
+    check(got, want, TOL[precision], f"e1 {precision}", ("phi", "psi"))
+    assert np.abs(got["ux"]).max() == 0.0 and np.abs(got["uy"]).max() == 0.0
+    sim.close()
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_random_small_fp64(seed):
     """Odd sizes, walls or periodic, r in {0,1,2}, linear or Langmuir EOS,
