@@ -97,10 +97,12 @@ class Server:
         self.order = order
         self.max_running_sites = max_running_sites
 
+    def _wait(self):
+        """Wait for the device work enqueued so far (the batch's stream)."""
+        self.batch.stream.synchronize()
+
     def run(self, requests: list[Request], keep_fields=frozenset(), clock=time.perf_counter,
             on_admit=None) -> tuple[list[Result], dict]:
-        import torch
-
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         waiting: collections.deque[Request] = collections.deque()
         running: dict[int, tuple[Request, float]] = {}
@@ -150,7 +152,7 @@ class Server:
                 if waiting:
                     raise RuntimeError("a request does not fit the empty batch")
                 break
-            torch.cuda.current_stream().synchronize()
+            self._wait()
             finished = [sid for sid in running if self.batch.remaining(sid) == 0]
             running.update(joined)
             running_sites += sum(_sites(r) for r, _ in joined.values())
