@@ -25,12 +25,15 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 # lbm.hip is compiled twice.  The second pass (LBM_F16_PART) holds only the
-# float16 step kernels, built with -ffp-contract=off: no multiply-add is
-# fused unless written as one, so a site's arithmetic gives the same bits in
-# every copy of the row code and float16 storage (which rounds
-# stochastically from all 32 bits of each value) stays independent of the
-# tile height.
-PASSES = (("main", []), ("f16", ["-DLBM_F16_PART", "-ffp-contract=off"]))
+# float16 step kernels, built with -ffp-contract=on: a multiply and an add
+# are fused only when they are one source expression, by the front end
+# (llvm.fmuladd), so every inlined copy of an expression is fused the same
+# way and a site's arithmetic gives the same bits in every copy of the row
+# code.  Float16 storage rounds stochastically from all 32 bits of each
+# value, so that is what keeps its results independent of the tile height.
+# (The back-end fusion across statements that the default allows depends on
+# the surrounding code; with it, copies of the row code differed by an ulp.)
+PASSES = (("main", []), ("f16", ["-DLBM_F16_PART", "-ffp-contract=on"]))
 
 
 def build(verbose: bool = False) -> str:

@@ -2167,11 +2167,13 @@ void launch_batch_prec(int c, int blocks, hipStream_t st, const void *desc,
 }  // namespace
 
 // The float16 step kernels are compiled in a second pass of this file
-// (LBM_F16_PART) without FP contraction.  Float16 storage rounds
-// stochastically from all 32 bits of each value, so every copy of the row
-// code must give the same bits for the results not to depend on the tile
-// height; the float32 and float64 kernels keep fused multiply-adds (1-2%
-// faster) and are tile-height independent with them.
+// (LBM_F16_PART) that fuses a multiply and an add only within one source
+// expression (-ffp-contract=on, done by the front end and so the same in
+// every inlined copy).  Float16 storage rounds stochastically from all 32
+// bits of each value, so every copy of the row code must give the same
+// bits for the results not to depend on the tile height; the float32 and
+// float64 kernels keep the compiler's default fusion (1-2% faster) and are
+// tile-height independent with it.
 namespace lbm_f16_part {
 hipError_t step(lbm_handle *h, int *waves_per_cu);
 void batch(int c, int blocks, hipStream_t st, const void *desc, const void *tiles,

@@ -24,7 +24,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 def device_asm(tmp_path, extra):
     from paper_2408_15654_amd import build
 
-    out = tmp_path / ("lbm%s.s" % ("_f16" if extra else ""))
+    out = tmp_path / ("lbm%d.s" % len(extra))
     cmd = [HIPCC, *build.FLAGS, *extra, "--offload-device-only", "-S", "-o", str(out),
            build.SOURCES[0]]
     subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
@@ -95,7 +95,9 @@ def hazards(lines):
                     reason="needs hipcc")
 def test_no_wide_store_data_rewritten_within_two_wait_states(tmp_path):
     total = 0
-    for extra in ([], ["-DLBM_F16_PART", "-ffp-contract=off"]):
+    from paper_2408_15654_amd import build
+
+    for _, extra in build.PASSES:
         found, n = hazards(device_asm(tmp_path, extra))
         total += n
         assert not found, found[:5]
