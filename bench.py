@@ -25,7 +25,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak (AMD spec)
 STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16dev": 2}
 FIELD_BYTES = {"fp64": 8, "fp32": 4, "fp16dev": 4}
-KERNEL_SOURCES = ("paper_2408_15654_amd/csrc/lbm.hip", "paper_2408_15654_amd/csrc/lbm_device.h")
+# what the step kernels are built from: sources and the build flags
+KERNEL_SOURCES = ("paper_2408_15654_amd/csrc/lbm.hip", "paper_2408_15654_amd/csrc/lbm_device.h",
+                  "paper_2408_15654_amd/build.py")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "lbm_step_kernel_many_drops_2048_{}_counters.txt")
 
 
