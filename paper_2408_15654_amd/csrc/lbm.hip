@@ -458,22 +458,22 @@ __device__ __forceinline__ void source_offsets(const Nine<R> &v, bool bot, bool 
 // Value of lane-1 / lane+1 of the wavefront: DPP wave shifts (one VALU op
 // per 32 bits; lane 0 / lane 63 receive 0, which is never used).
 __device__ __forceinline__ float from_left(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float from_right(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double from_left(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x138, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x138, 0xf, 0xf, true);
   return __longlong_as_double((long long)((unsigned long long)(unsigned)lo |
                                           ((unsigned long long)(unsigned)hi << 32)));
 }
 __device__ __forceinline__ double from_right(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x130, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x130, 0xf, 0xf, true);
   return __longlong_as_double((long long)((unsigned long long)(unsigned)lo |
                                           ((unsigned long long)(unsigned)hi << 32)));
 }
@@ -768,6 +768,11 @@ __device__ __forceinline__ float half_lo(unsigned w) {
 __device__ __forceinline__ float half_hi(unsigned w) {
   return float(__builtin_bit_cast(_Float16, (unsigned short)(w >> 16)));
 }
+// A widened float16 value times a scale, rounded once: written as a fused
+// multiply-add with +0 so that the widening and the product are one
+// mixed-precision instruction (v_fma_mix_f32).  The result is the rounded
+// product, except that a product of -0 becomes +0.
+__device__ __forceinline__ float scale_half(float h, float s) { return __builtin_fmaf(h, s, 0.0f); }
 __device__ __forceinline__ unsigned halves(float lo, float hi) {
   const unsigned short a = __builtin_bit_cast(unsigned short, _Float16(lo)),
                        b = __builtin_bit_cast(unsigned short, _Float16(hi));
@@ -816,7 +821,7 @@ __device__ __forceinline__ unsigned halves_sr(float lo, float hi, unsigned key) 
 __device__ __forceinline__ void pack_fg(const float *f, const float *g, float sf, float sg,
                                         unsigned site, unsigned *w, float &amax) {
 #pragma clang fp contract(off)
-  float ef = 0.f, eg = 0.f;
+  float ef = -0.f, eg = -0.f;  // -0 + x is x: the first sum needs no add
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     const float vf = f[i] * sf, vg = g[i] * sg;
@@ -874,27 +879,25 @@ struct Pull2 {
   // are rounded here (no contraction into the sums that use them), so the
   // result does not depend on which copy of the row code a site runs in.
   static __device__ __forceinline__ void decode_fg(const Scales<P> &sc, R (*f)[9], R (*g)[9]) {
-#pragma clang fp contract(off)
     if constexpr (sizeof(S) == 2) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const unsigned w0 = __float_as_uint(f[0][i]), w1 = __float_as_uint(f[1][i]);
-        f[0][i] = half_lo(w0) * sc.fi;
-        g[0][i] = half_hi(w0) * sc.gi;
-        f[1][i] = half_lo(w1) * sc.fi;
-        g[1][i] = half_hi(w1) * sc.gi;
+        f[0][i] = scale_half(half_lo(w0), sc.fi);
+        g[0][i] = scale_half(half_hi(w0), sc.gi);
+        f[1][i] = scale_half(half_lo(w1), sc.fi);
+        g[1][i] = scale_half(half_hi(w1), sc.gi);
       }
     }
   }
   // float16 storage: unpack and scale what h() loaded
   static __device__ __forceinline__ void decode_h(R inv, R (*h)[8]) {
-#pragma clang fp contract(off)
     if constexpr (sizeof(S) == 2) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         const unsigned w = __float_as_uint(h[0][k]);
-        h[0][k] = half_lo(w) * inv;
-        h[1][k] = half_hi(w) * inv;
+        h[0][k] = scale_half(half_lo(w), inv);
+        h[1][k] = scale_half(half_hi(w), inv);
       }
     }
   }
