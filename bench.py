@@ -241,6 +241,7 @@ def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), loa
     from paper_2408_15654_amd import lbm, serve
 
     out = []
+    refs = {}  # float64 re-runs (and perturbed twins), shared by runs of the same problem
     for prec in precisions:
         # capacity: the batched rate on the stream's own problem mix
         reqs, _ = serve.serving_stream(n=n, rate=1.0, precision=prec, max_steps=max_steps)
@@ -263,7 +264,7 @@ def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), loa
         reqs, rate = serve.serving_stream(n=n, precision=prec, max_steps=max_steps,
                                           offered_MLUPS=load * cap)
         check = {r.rid for r in reqs if r.rid % 10 == 0}
-        for gb in budgets_gb if prec == "fp32" else budgets_gb[-1:]:
+        for gb in budgets_gb:
             srv = serve.Server(int(gb) << 30, max_instances=512, chunk=64, **SERVE_POLICY)
             results, stats = srv.run(reqs, keep_fields=check)
             srv.close()
@@ -276,17 +277,24 @@ def serving_bench(n=200, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"), loa
                 if res.fields is None:
                     continue
                 req = by_id[res.rid]
-                ref = []
-                # the float64 re-run, and a twin whose initial phi carries a
-                # relative perturbation of 1e-10: how far two float64 runs
-                # drift apart measures how much the flow amplifies rounding
-                for eps in (0.0, 1e-10):
-                    phi0 = req.fields0[0] * (1.0 + eps * rng.standard_normal(req.fields0[0].shape))
-                    sim = lbm.Simulation(dict(req.params, precision="fp64"))
-                    sim.init_fields(phi0, *req.fields0[1:])
-                    sim.step(req.steps)
-                    ref.append(sim.read_fields())
-                    sim.close()
+                key = (req.steps, json.dumps(dict(req.params, precision="fp64"), sort_keys=True),
+                       req.fields0[0].tobytes(), req.fields0[1].tobytes())
+                if key not in refs:
+                    # the float64 re-run, and a twin whose initial phi carries
+                    # a relative perturbation of 1e-10: how far two float64
+                    # runs drift apart measures how much the flow amplifies
+                    # rounding
+                    ref = []
+                    for eps in (0.0, 1e-10):
+                        phi0 = req.fields0[0] * (
+                            1.0 + eps * rng.standard_normal(req.fields0[0].shape))
+                        sim = lbm.Simulation(dict(req.params, precision="fp64"))
+                        sim.init_fields(phi0, *req.fields0[1:])
+                        sim.step(req.steps)
+                        ref.append(sim.read_fields())
+                        sim.close()
+                    refs[key] = ref
+                ref = refs[key]
                 errs.append(rel_errors(res.fields, ref[0]))
                 spread.append(rel_errors(ref[1], ref[0]))
             worst = {k: max(e[k] for e in errs) for k in ("phi", "psi", "u")} if errs else {}
@@ -509,9 +517,9 @@ def main():
         # the batched sweep at its full 10000 steps (untuned and tuned)
         out["batched"] = batched_sweep(steps=10000)
         progress(f"batched sweep: {out['batched']['batched_tuned_MLUPS']} MLUPS")
-        # the serving stream, 100 solves of up to 10000 steps: float32 with a
-        # small (2 GB) and a large (64 GB) HBM budget, float16 deviations
-        # with the large one
+        # the serving stream, 100 solves of up to 10000 steps: float32 and
+        # float16 deviations, each with a small (2 GB) and a large (64 GB)
+        # HBM budget
         runs = serving_bench(n=100, budgets_gb=(2, 64), precisions=("fp32", "fp16dev"),
                              max_steps=10000, quiet=True)
         main = [r for r in runs if r["precision"] == "fp32" and r["budget_GB"] == 64][0]
