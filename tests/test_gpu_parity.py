@@ -280,7 +280,9 @@ def test_largest_grid_equals_its_tiled_small_copy(precision):
     Bitwise for float64 and float32 storage; float16 storage draws its
     rounding bits per site, so there phi, psi and u are held to the float16
     bar (P, a diagnostic near 1e-8 here, is not under it).  Any offset that
-    overflows at the largest sizes breaks the copy."""
+    overflows at the largest sizes breaks the copy.  The large fields are
+    also held, at the storage's bar, to the oracle's run of the small field,
+    tiled (the problem is translation invariant)."""
     n, p = MAX_GRID[precision]
     steps = 3
     pr = W.c3_many_drops(precision=precision, nx=p, ny=p, ndrops=2)
@@ -292,6 +294,9 @@ def test_largest_grid_equals_its_tiled_small_copy(precision):
     got = sim.read_fields()
     sim.close()
     del sim
+    _, ref = run_oracle(pr, steps)
+    check(got, {k: np.tile(ref[k], reps) for k in ("phi", "psi", "ux", "uy")}, TOL[precision],
+          f"largest grid {precision} {n}^2 against the oracle")
     want = {k: np.tile(small[k], reps) for k in ("phi", "psi", "ux", "uy", "P")}
     if precision == "fp16dev":
         err = errors(got, want, FIELDS)
@@ -539,3 +544,4 @@ def test_integer_translation_is_bitwise(precision, nx, ny):
     sim.close()
     for k in ("phi", "psi", "ux", "uy", "P"):
         assert np.array_equal(np.roll(a[k], (dy, dx), axis=(0, 1)), b[k]), k
+
