@@ -502,7 +502,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": sim.step_kernel_name(),
-                     "kernel_ms_per_launch": round(per_launch_ms, 4)},
+                     "kernel_ms_per_launch": round(per_launch_ms, 4),
+                     # the counter bytes (reads past L2 and writes, halo
+                     # re-reads included) over this run's launch time
+                     "traffic_GBps": (round(traffic / (per_launch_ms * 1e-3) / 1e9, 1)
+                                      if traffic else None),
+                     "traffic_frac": (round(traffic / (per_launch_ms * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS, 4) if traffic else None)},
         "conservation": {"sum_phi_rel_drift": (m1["sum_phi"] - m0["sum_phi"]) / m0["sum_phi"],
                          "sum_psi_rel_drift": (m1["sum_psi"] - m0["sum_psi"]) / m0["sum_psi"],
                          "steps": m1["step"]},
