@@ -168,6 +168,16 @@ __device__ __forceinline__ void wide_store_guard() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// Byte offset of a lane whose buffer stores must not land.  The hardware
+// discards a buffer store whose offset is past the resource's range: it
+// checks soffset + voffset (+ 4 per further dword) against the resource's
+// byte count, without 32-bit wraparound (measured on MI355X for offsets up
+// to 0xFFFFFFF0 with soffset 0 to 2^31), and no memory request is made.
+// Every resource of the step covers at most kDropped bytes (lbm_create
+// checks it), so kDropped, and kDropped plus the few bytes added within a
+// record (at most 32, below 2^32 still), is past all of them.
+constexpr unsigned kDropped = 0xFFFFFF00u;
+
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes),
                                            0x00020000);
@@ -743,24 +753,6 @@ __device__ __forceinline__ void static_for(F &&f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-// v on lanes where own is set, lane L's v elsewhere (lane L is an interior
-// lane of every strip).
-template <int L>
-__device__ __forceinline__ unsigned lane_pick(bool own, unsigned v) {
-  const unsigned o = __builtin_amdgcn_readlane(v, L);
-  return own ? v : o;
-}
-template <int L>
-__device__ __forceinline__ float lane_pick(bool own, float v) {
-  return __uint_as_float(lane_pick<L>(own, __float_as_uint(v)));
-}
-template <int L>
-__device__ __forceinline__ double lane_pick(bool own, double v) {
-  const unsigned lo = lane_pick<L>(own, unsigned(__double2loint(v)));
-  const unsigned hi = lane_pick<L>(own, unsigned(__double2hiint(v)));
-  return __hiloint2double(int(hi), int(lo));
-}
-
 // Float16 halves of a 32-bit word.
 __device__ __forceinline__ float half_lo(unsigned w) {
   return float(__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu)));
@@ -1186,13 +1178,11 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
     rebuild_below();
   }
 
-  // Stores are issued by every lane: a halo lane repeats lane HL's values
-  // at lane HL's address (identical bits, same cache line).
-  const ColOff cs = {lane_pick<HL>(interior, co.p0), 0u, 0u, lane_pick<HL>(interior, co.h0),
-                     0u, 0u};
-  const unsigned brest_s = lane_pick<HL>(interior, brest),
-                 baux_s = lane_pick<HL>(interior, baux);
-  auto lp = [&](R v) { return lane_pick<HL>(interior, v); };
+  // Stores are issued by every lane (the same memory operations on every
+  // path); a halo lane's offsets are kDropped, so the hardware discards its
+  // part and only interior lanes write.
+  const ColOff cs = {interior ? co.p0 : kDropped, 0u, 0u, interior ? co.h0 : kDropped, 0u, 0u};
+  const unsigned brest_s = interior ? brest : kDropped, baux_s = interior ? baux : kDropped;
   bool bad = false;
 
   auto row_step = [&](int y, auto prefetch) {
@@ -1321,12 +1311,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
         pack_fg(dc[0], qc[0], sc.f, sc.g, unsigned(y) * unsigned(nx) + xc, w, amax);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-          __builtin_amdgcn_raw_buffer_store_b32(lane_pick<HL>(interior, w[i]), rdst, cs.p0,
+          __builtin_amdgcn_raw_buffer_store_b32(w[i], rdst, cs.p0,
                                                 rcs + unsigned(i) * nxb, P::kStorePol);
       } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-          PairIO<S>::template store<P::kStorePol>(S(lp(dc[0][i])), S(lp(qc[0][i])), rdst, cs.p0,
+          PairIO<S>::template store<P::kStorePol>(S(dc[0][i]), S(qc[0][i]), rdst, cs.p0,
                            rcs + unsigned(i) * nxb);
       }
       if constexpr (NS && P::SCALED) {
@@ -1336,43 +1326,42 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
           const float v = h[0][i] * sc.h;
           amax = fmaxf(amax, fabsf(v));
           __builtin_amdgcn_raw_buffer_store_b16(
-              (unsigned short)(lane_pick<HL>(interior, halves_sr(v, 0.f, key + unsigned(i))) &
-                               0xffffu),
+              (unsigned short)(halves_sr(v, 0.f, key + unsigned(i)) & 0xffffu),
               rdst, cs.h0, rcs + hb + unsigned(i) * nxh, P::kStorePol);
         }
       } else if constexpr (NS) {
 #pragma unroll
         for (int i = 0; i < 8; ++i)
-          bst<P>(lp(h[0][i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh);
+          bst<P>(h[0][i], rdst, cs.h0, rcs + hb + unsigned(i) * nxh);
       }
       if constexpr (P::HDEV && NS) {  // (phi, psi, P, rho ux) and rho uy
-        QuadIO::store<P::kStorePol>(lp(phc[0]), lp(psc[0]), lp(hn.pr[0]), lp(hn.jx[0]), rdrest,
+        QuadIO::store<P::kStorePol>(phc[0], psc[0], hn.pr[0], hn.jx[0], rdrest,
                                     brest_s, unsigned(y) * rrow);
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(lp(hn.jy[0])), rdrest,
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(hn.jy[0]), rdrest,
                                               brest_s + 4 * EA, unsigned(y) * rrow,
                                               P::kStorePol);
       } else {
-        PairIO<A>::template store<P::kStorePol>(A(lp(phc[0])), A(lp(psc[0])), rdrest, brest_s,
+        PairIO<A>::template store<P::kStorePol>(A(phc[0]), A(psc[0]), rdrest, brest_s,
                                                 unsigned(y) * rrow);
       }
       if constexpr (!P::HDEV && NS)
-        PairIO<A>::template store<P::kStorePol>(A(lp(oux[0])), A(lp(ouy[0])), raux, baux_s,
+        PairIO<A>::template store<P::kStorePol>(A(oux[0]), A(ouy[0]), raux, baux_s,
                                                 unsigned(y) * arow);
     } else if constexpr (sizeof(S) == 4) {
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        QuadIO::store<P::kStorePol>(lp(dc[0][i]), lp(qc[0][i]), lp(dc[1][i]), lp(qc[1][i]), rdst,
+        QuadIO::store<P::kStorePol>(dc[0][i], qc[0][i], dc[1][i], qc[1][i], rdst,
                                     cs.p0, rcs + unsigned(i) * nxb);
       if constexpr (NS) {
 #pragma unroll
         for (int i = 0; i < 8; ++i)
           PairIO<S>::template store<P::kStorePol>(
-              lp(h[0][i]), lp(h[1][i]), rdst, cs.h0, rcs + hb + unsigned(i) * nxh);
+              h[0][i], h[1][i], rdst, cs.h0, rcs + hb + unsigned(i) * nxh);
       }
-      QuadIO::store<P::kStorePol>(lp(phc[0]), lp(psc[0]), lp(phc[1]), lp(psc[1]), rdrest,
+      QuadIO::store<P::kStorePol>(phc[0], psc[0], phc[1], psc[1], rdrest,
                                   brest_s, unsigned(y) * rrow);
       if constexpr (NS)
-        QuadIO::store<P::kStorePol>(lp(oux[0]), lp(ouy[0]), lp(oux[1]), lp(ouy[1]), raux,
+        QuadIO::store<P::kStorePol>(oux[0], ouy[0], oux[1], ouy[1], raux,
                                     baux_s, unsigned(y) * arow);
     } else {  // float16 deviations, scaled: four halves per (f, g) plane, two per h plane
       const unsigned site = unsigned(y) * unsigned(nx) + xc;
@@ -1382,8 +1371,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         u32x2 w;
-        w[0] = lane_pick<HL>(interior, w0[i]);
-        w[1] = lane_pick<HL>(interior, w1[i]);
+        w[0] = w0[i];
+        w[1] = w1[i];
         __builtin_amdgcn_raw_buffer_store_b64(w, rdst, cs.p0, rcs + unsigned(i) * nxb,
                                               P::kStorePol);
       }
@@ -1393,22 +1382,22 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
           const float v0 = h[0][i] * sc.h, v1 = h[1][i] * sc.h;
           amax = fmaxf(amax, fmaxf(fabsf(v0), fabsf(v1)));
           __builtin_amdgcn_raw_buffer_store_b32(
-              lane_pick<HL>(interior, halves_sr(v0, v1, site * 32u + 16u + unsigned(i))),
+              halves_sr(v0, v1, site * 32u + 16u + unsigned(i)),
               rdst, cs.h0, rcs + hb + unsigned(i) * nxh, P::kStorePol);
         }
       }
       if constexpr (P::HDEV && NS) {
         // the two 5-float rest records (40 bytes) as 16 + 16 + 8 bytes
-        QuadIO::store<P::kStorePol>(lp(phc[0]), lp(psc[0]), lp(hn.pr[0]), lp(hn.jx[0]), rdrest,
+        QuadIO::store<P::kStorePol>(phc[0], psc[0], hn.pr[0], hn.jx[0], rdrest,
                                     brest_s, unsigned(y) * rrow);
-        QuadIO::store<P::kStorePol>(lp(hn.jy[0]), lp(phc[1]), lp(psc[1]), lp(hn.pr[1]), rdrest,
+        QuadIO::store<P::kStorePol>(hn.jy[0], phc[1], psc[1], hn.pr[1], rdrest,
                                     brest_s + 4 * EA, unsigned(y) * rrow);
-        PairIO<A>::template store<P::kStorePol>(lp(hn.jx[1]), lp(hn.jy[1]), rdrest,
+        PairIO<A>::template store<P::kStorePol>(hn.jx[1], hn.jy[1], rdrest,
                                                 brest_s + 8 * EA, unsigned(y) * rrow);
       } else {
 #pragma unroll
         for (int k = 0; k < K; ++k)
-          PairIO<A>::template store<P::kStorePol>(lp(phc[k]), lp(psc[k]), rdrest,
+          PairIO<A>::template store<P::kStorePol>(phc[k], psc[k], rdrest,
                                                   brest_s + unsigned(k) * P::kRest * EA,
                                                   unsigned(y) * rrow);
       }
@@ -1957,11 +1946,12 @@ const char *validate(const lbm_params *p) {
   if (p->flow != LBM_FLOW_NS && p->flow != LBM_FLOW_PRESCRIBED) return "unknown flow";
   {
     // the step kernel addresses each population copy through one buffer
-    // resource with 32-bit byte offsets
+    // resource with 32-bit byte offsets, and its halo lanes store at
+    // kDropped, which must lie past every resource
     const unsigned long long sites = (unsigned long long)p->nx * p->ny;
-    if (kPlanes * sites * storage_size(p->precision) > 0xFFFFFFFFull)
+    if (kPlanes * sites * storage_size(p->precision) > kDropped)
       return "grid too large: 26 population planes must fit in 4 GiB";
-    if (rest_fields(p->precision) * sites * field_size(p->precision) > 0xFFFFFFFFull)
+    if (rest_fields(p->precision) * sites * field_size(p->precision) > kDropped)
       return "grid too large: the rest records must fit in 4 GiB";
   }
   if (!(p->phiA > p->phiB)) return "phiA must exceed phiB";
