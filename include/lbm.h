@@ -89,7 +89,10 @@ typedef enum { LBM_FLOW_NS = 0, LBM_FLOW_PRESCRIBED = 1 } lbm_flow;
  *   1/s2^h = mu/(rho c_s^2) + 1/2 (Eq. (33), per site, tau_f = 3 mu/rho + 1/2)
  * The remaining rates of S^k (Eq. (34)) are free and taken from s_free. */
 typedef struct {
-  int32_t nx, ny;       /* lattice sites; nx, ny >= 3; x is periodic        */
+  int32_t nx, ny;       /* lattice sites; nx, ny >= 3; x is periodic; one
+                           copy of the 26 population planes must stay within
+                           0xFFFFFF00 bytes (26 nx ny x 8, 4 or 2 bytes by
+                           precision: squares up to 4544^2, 6426^2, 9088^2) */
   int32_t walls_y;      /* 0: periodic in y; 1: half-way bounce-back walls
                            below row 0 and above row ny-1 (Sec. 4)          */
   int32_t eos;          /* lbm_eos                                          */
