@@ -91,6 +91,20 @@ def test_largest_accepted_grids():
         assert lib.lbm_workspace_bytes(ctypes.byref(big)) == 0, prec
 
 
+def test_grids_whose_halo_offset_would_land_are_refused():
+    """Halo lanes of the step store at byte offset 0xFFFFFF00, past every
+    buffer, where the hardware discards them; a grid whose population planes
+    reach that offset (though they fit in 4 GiB) is refused."""
+    lib = lbm.load()
+    pr = workloads.c1_stationary_drop()
+    for prec, nx, ny, bytes_per_pop in (("fp32", 5641, 7321, 4), ("fp64", 11, 1877171, 8),
+                                        ("fp16dev", 8969, 9209, 2)):
+        n = 26 * nx * ny * bytes_per_pop
+        assert 0xFFFFFF00 < n <= 0xFFFFFFFF
+        c = lbm.to_c_params(dict(pr.params, nx=nx, ny=ny, precision=prec))
+        assert lib.lbm_workspace_bytes(ctypes.byref(c)) == 0, prec
+
+
 def test_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(ImportError):
         lbm._lib_backup = lbm._lib
