@@ -1232,7 +1232,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
                         walls && y == ny - 1, b);
 #pragma unroll
         for (int i = 0; i < 8; ++i) h[k][i] += b[i];
-        const R irho = R(1) / (p.rhoB + p.drho * (X1[k] - p.phiB));
+        const R irho = recip(p.rhoB + p.drho * (X1[k] - p.phiB));
         uxp[k] = Hc.jx[k] * irho;
         uyp[k] = Hc.jy[k] * irho;
       });

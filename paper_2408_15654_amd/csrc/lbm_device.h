@@ -56,6 +56,24 @@ template <>
 __device__ __forceinline__ float third_of<float>(float x) {
   return __builtin_fmaf(x, 0x1.555556p-2f, x * -0x1.555556p-27f);
 }
+// 1/x.  float32: the hardware reciprocal (within 1 ulp) refined by one
+// Newton step in fused multiply-adds, 3 instructions instead of the ~10 of
+// a correctly rounded division, and within an ulp of it (on the parity
+// problems it gave the rounded quotient wherever it is used: their results
+// are bitwise those of the division).  Where many sites share one x (a
+// uniform phase) they would share an error too, as they share the rounding
+// of a division: a relative 1e-7 in u or in a relaxation rate, with no
+// large term to amplify it (unlike the 1/3 of third_of).  float64 keeps the
+// division.
+template <class R>
+__device__ __forceinline__ R recip(R x) {
+  return R(1) / x;
+}
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+}
 template <class R>
 __device__ __forceinline__ R ninth_of(R x) {
   return x * (R(1) / R(9));
@@ -128,7 +146,7 @@ template <class R>
 __device__ __forceinline__ void normal_delta(const Phys<R>& p, R phi, R gfx, R gfy, R& nx,
                                              R& ny, R& delta) {
   const R gn = sqrt(gfx * gfx + gfy * gfy);
-  const R inv = R(1) / (gn + p.eps_n);
+  const R inv = recip(gn + p.eps_n);
   nx = gfx * inv;
   ny = gfy * inv;
   delta = p.c4W * ((p.phiA - phi) * (phi - p.phiB));
@@ -187,7 +205,7 @@ __device__ __forceinline__ void site_front(const Phys<R>& p, Front<R>& s, R phi,
   const R sumh = ((h[0] + h[2]) + (h[1] + h[3])) + ((h[4] + h[6]) + (h[5] + h[7]));
   s.jx = jx0 + R(0.5) * s.Fx;
   s.jy = jy0 + R(0.5) * s.Fy;
-  const R irho = R(1) / rho;
+  const R irho = recip(rho);
   s.ux = s.jx * irho;
   s.uy = s.jy * irho;
   const R ux = s.ux, uy = s.uy;
@@ -218,7 +236,7 @@ __device__ __forceinline__ void site_front(const Phys<R>& p, Front<R>& s, R phi,
                   R(1) / R(3) * (s.dTxx + s.dTyy));
   // Eq. (33): 1/s2 = 3 mu/rho + 1/2
   const R mu = p.muB + p.dmu * (phi - p.phiB);
-  s.s2h = R(1) / (R(3) * mu * irho + R(0.5));
+  s.s2h = recip(R(3) * mu * irho + R(0.5));
 }
 
 // MRT collision of a convection-diffusion LB (Eqs. (21), (25)) in raw-moment
