@@ -630,6 +630,16 @@ struct QuadIO {
   }
 };
 
+// A wave-uniform integer the compiler cannot see through.  The row loop
+// passes the row number through it, so that the byte offsets derived from
+// the row (one per population plane and record) are computed where they are
+// used, by scalar adds, instead of each becoming an induction variable of
+// its own: those outnumbered the scalar registers and were kept in vector
+// lanes, one v_readlane per use.
+__device__ __forceinline__ int opaque_row(int y) {
+  return __builtin_amdgcn_readfirstlane(y);
+}
+
 // Byte offsets of one row in the step kernel's three groups.
 struct RowOff {
   unsigned m, c, p;  // population rows y-1, y, y+1
@@ -1446,7 +1456,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
   // a loop body with 1% fewer instructions: 1.5% faster for float32 and 1%
   // for float64 storage on the 2048x2048 field, same bits.)
   int y = y0;
-  for (int i = y0; i < y1 - 1; ++i, ++y) row_step(y, BoolC<true>{});
+  for (int i = y0; i < y1 - 1; ++i, ++y) row_step(opaque_row(y), BoolC<true>{});
   row_step(y, BoolC<false>{});  // the last row prefetches nothing
   if (bad) *a.flag = 1;
 }
