@@ -243,12 +243,23 @@ void lbm_destroy(lbm_handle *h);
 const char *lbm_last_error(const lbm_handle *h);
 
 /* Rows of lattice each wavefront of the step kernel walks through (its tile
- * height).  0 restores the default: for a grid too small to fill the
- * device, the shortest tiles whose wavefronts all fit on it at once (a step
- * then takes about one wavefront's walk down its tile); otherwise a height
- * tuned for large grids.  Results do not depend on the tile height.
+ * height).  The rows are cut into one band per XCD (the hardware deals
+ * workgroups to the 8 XCDs round-robin); each band is walked in tiles of
+ * this height and ends in a few 1-row tiles, so the launch drains quickly.
+ * 0 restores the default plan: for a grid too small to fill the device, the
+ * shortest tiles whose wavefronts all fit on it at once (a step then takes
+ * about one wavefront's walk down its tile); for float16 storage with two
+ * columns per lane, one tile per wavefront slot of the device when such
+ * tiles are at most 24 rows high; otherwise a height tuned for large grids.
+ * Results do not depend on the tiling.
  * Errors: LBM_EINVAL (< 0 or > 4096). */
 lbm_status lbm_set_tile_rows(lbm_handle *h, int32_t rows);
+
+/* The single-grid tile plan in use: plan[0] the tile height, plan[1] the
+ * rows at the end of each XCD's band walked in short tiles, plan[2] the
+ * height of those (the last may be lower).  plan is host memory of 3
+ * int32_t, written only on success.  Errors: LBM_EINVAL (NULL). */
+lbm_status lbm_get_tile_plan(const lbm_handle *h, int32_t *plan);
 
 /* The step kernel variant lbm_step launches for this handle, named as a
  * profiler prints its template arguments, e.g.

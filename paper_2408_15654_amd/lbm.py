@@ -70,7 +70,7 @@ EXPORTS = ("lbm_workspace_bytes", "lbm_create", "lbm_init_fields", "lbm_step",
            "lbm_read_fields", "lbm_moments", "lbm_moments_async", "lbm_state_bytes",
            "lbm_get_state",
            "lbm_set_state", "lbm_destroy", "lbm_last_error", "lbm_set_tile_rows",
-           "lbm_step_kernel_name")
+           "lbm_get_tile_plan", "lbm_step_kernel_name")
 
 _lib = None
 
@@ -109,11 +109,12 @@ def load(path: str = LIB_PATH):
     lib.lbm_last_error.argtypes = [H]
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_set_tile_rows.argtypes = [H, ctypes.c_int32]
+    lib.lbm_get_tile_plan.argtypes = [H, ctypes.POINTER(ctypes.c_int32)]
     lib.lbm_step_kernel_name.argtypes = [H]
     lib.lbm_step_kernel_name.restype = ctypes.c_char_p
     for name in ("lbm_create", "lbm_init_fields", "lbm_step", "lbm_read_fields",
                  "lbm_moments", "lbm_moments_async", "lbm_get_state", "lbm_set_state",
-                 "lbm_set_tile_rows"):
+                 "lbm_set_tile_rows", "lbm_get_tile_plan"):
         getattr(lib, name).restype = ctypes.c_int
     # batches
     B, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -280,6 +281,12 @@ class Simulation:
 
     def set_tile_rows(self, rows: int):
         self._check(self.lib.lbm_set_tile_rows(self._handle, int(rows)))
+
+    def tile_plan(self) -> tuple[int, int, int]:
+        """(tile height, rows per XCD band in short tiles, their height)."""
+        plan = (ctypes.c_int32 * 3)()
+        self._check(self.lib.lbm_get_tile_plan(self._handle, plan))
+        return tuple(plan)
 
     def step_kernel_name(self) -> str:
         return self.lib.lbm_step_kernel_name(self._handle).decode()

@@ -73,6 +73,10 @@ def test_workspace_bytes_and_validation_without_device():
     # misaligned workspace
     st = lib.lbm_create(ctypes.byref(c), ctypes.c_void_p(8), 1 << 40, None, ctypes.byref(h))
     assert st == lbm.LBM_EINVAL
+    # queries on a NULL handle
+    plan = (ctypes.c_int32 * 3)(7, 7, 7)
+    assert lib.lbm_get_tile_plan(None, plan) == lbm.LBM_EINVAL
+    assert tuple(plan) == (7, 7, 7)
 
 
 def test_largest_accepted_grids():

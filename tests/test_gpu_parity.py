@@ -306,6 +306,27 @@ def test_largest_grid_equals_its_tiled_small_copy(precision):
             assert np.array_equal(got[k], want[k]), k
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16dev"])
+def test_default_tile_plan_gives_the_bits_of_one_row_tiles(precision):
+    """2048x1024: the default plan cuts each XCD's 128-row band into tall
+    tiles followed by 1-row tiles (float32 storage: 2-row tiles and 15 rows
+    of 1-row tiles; float16 storage: one tile per wavefront slot, 15 tiles
+    of 8 rows, then 8 rows of 1-row tiles, on a 256-CU device).  Bitwise the
+    same fields as 1-row tiles everywhere."""
+    pr = W.c3_many_drops(precision=precision, nx=2048, ny=1024, ndrops=200)
+    sim = lbm.Simulation(dict(pr.params, precision=precision))
+    plan = sim.tile_plan()
+    print(f"{precision} 2048x1024 tile plan {plan}", flush=True)
+    assert plan[0] > 1 and plan[1] > 0 and plan[2] == 1, plan
+    sim.init_fields(*pr.fields0)
+    sim.step(12)
+    got = sim.read_fields()
+    sim.close()
+    _, want = run_gpu(pr, precision, 12, rows=1)
+    for k in ("phi", "psi", "ux", "uy", "P"):
+        assert np.array_equal(got[k], want[k]), k
+
+
 def test_tile_height_does_not_change_results():
     """Each site's arithmetic is independent of the tiling: bitwise equal."""
     pr = W.random_small(3, nx=150, ny=70, steps=25)
