@@ -306,14 +306,21 @@ def test_largest_grid_equals_its_tiled_small_copy(precision):
             assert np.array_equal(got[k], want[k]), k
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16dev"])
-def test_default_tile_plan_gives_the_bits_of_one_row_tiles(precision):
+@pytest.mark.parametrize("precision,walls", [("fp32", False), ("fp16dev", False),
+                                             ("fp32", True), ("fp16dev", True)])
+def test_default_tile_plan_gives_the_bits_of_one_row_tiles(precision, walls):
     """2048x1024: the default plan cuts each XCD's 128-row band into tall
     tiles followed by 1-row tiles (float32 storage: 2-row tiles and 15 rows
     of 1-row tiles; float16 storage: one tile per wavefront slot, 15 tiles
     of 8 rows, then 8 rows of 1-row tiles, on a 256-CU device).  Bitwise the
-    same fields as 1-row tiles everywhere."""
-    pr = W.c3_many_drops(precision=precision, nx=2048, ny=1024, ndrops=200)
+    same fields as 1-row tiles everywhere: periodic drops, and a dense drop
+    on the moving bottom wall (the top wall row is then walked by a 1-row
+    tile at the end of the last band)."""
+    if walls:
+        pr = W.random_small(7, nx=2048, ny=1024, walls=True, wall_drop=True,
+                            precision=precision)
+    else:
+        pr = W.c3_many_drops(precision=precision, nx=2048, ny=1024, ndrops=200)
     sim = lbm.Simulation(dict(pr.params, precision=precision))
     plan = sim.tile_plan()
     print(f"{precision} 2048x1024 tile plan {plan}", flush=True)
