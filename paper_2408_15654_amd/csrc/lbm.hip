@@ -265,7 +265,7 @@ struct StepArgs {
   typename P::A *aux;
   int *flag;
   int nx, ny, walls;
-  int nstrips, ntiles, rows;
+  int nstrips, rows;
   int tail_rows, tail_h;  // single-grid launches: short chunks at each band's end
 };
 
@@ -2162,7 +2162,6 @@ hipError_t launch_step(lbm_handle *h, int *waves_per_cu) {
   a.walls = h->p.walls_y;
   a.nstrips = strips_of(h->p);
   a.rows = h->rows;
-  a.ntiles = a.nstrips * ((h->p.ny + a.rows - 1) / a.rows);
   a.tail_rows = h->tail_rows;
   a.tail_h = h->tail_h;
   hipLaunchKernelGGL((lbm_step_kernel<P, K, GENR, HAS_S, NS>), dim3(step_grid<P>(a)),
@@ -2837,7 +2836,6 @@ StepArgs<P> step_args(const lbm_handle *h, int cur) {
   a.walls = h->p.walls_y;
   a.nstrips = strips_of(h->p);
   a.rows = h->rows;
-  a.ntiles = a.nstrips * ((h->p.ny + a.rows - 1) / a.rows);
   a.tail_rows = 0;  // batched tiles come from the tile list
   a.tail_h = 1;
   return a;
