@@ -1467,13 +1467,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<P> &a, const int strip,
 constexpr int kXcds = 8;
 
 // The rows one XCD walks in a single-grid step, cut into chunks: `rows`
-// high, then short chunks (tail_h high, the last one possibly lower) over at
-// least tail_rows rows at the band's end.  Band x holds rows
-// [x ny / 8, (x + 1) ny / 8).
+// high (the last one possibly lower) up to the band's last tail_rows rows,
+// then short chunks (tail_h high, the last one possibly lower) over those.
+// Band x holds rows [x ny / 8, (x + 1) ny / 8).
 struct Band {
   int y0, y1;    // the band's rows
-  int nlong;     // chunks of `rows` rows from y0
   int ys;        // first row of the short chunks
+  int nlong;     // chunks of at most `rows` rows in [y0, ys)
   int nchunks;   // long and short
 };
 
@@ -1481,10 +1481,10 @@ __host__ __device__ inline Band band_of(int x, int ny, int rows, int tail_rows, 
   Band b;
   b.y0 = int((long long)x * ny / kXcds);
   b.y1 = int((long long)(x + 1) * ny / kXcds);
-  const int n = b.y1 - b.y0;
-  b.nlong = (n - min(tail_rows, n)) / rows;
-  b.ys = b.y0 + b.nlong * rows;
-  b.nchunks = b.nlong + (b.y1 - b.ys + tail_h - 1) / tail_h;
+  const int t = min(tail_rows, b.y1 - b.y0);
+  b.ys = b.y1 - t;
+  b.nlong = (b.ys - b.y0 + rows - 1) / rows;
+  b.nchunks = b.nlong + (t + tail_h - 1) / tail_h;
   return b;
 }
 
@@ -1520,7 +1520,7 @@ lbm_step_kernel(const StepArgs<P> a) {
   if (chunk >= b.nchunks) return;  // whole wavefronts only
   const bool full = chunk < b.nlong;
   const int y0 = full ? b.y0 + chunk * a.rows : b.ys + (chunk - b.nlong) * a.tail_h;
-  const int y1 = full ? y0 + a.rows : min(y0 + a.tail_h, b.y1);
+  const int y1 = full ? min(y0 + a.rows, b.ys) : min(y0 + a.tail_h, b.y1);
   step_tile<P, K, GENR, HAS_S, NS>(a, tile - chunk * a.nstrips, y0, y1);
 }
 
