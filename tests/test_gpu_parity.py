@@ -334,6 +334,21 @@ def test_default_tile_plan_gives_the_bits_of_one_row_tiles(precision, walls):
         assert np.array_equal(got[k], want[k]), k
 
 
+@pytest.mark.parametrize("ny", [5, 9, 43, 130])
+@pytest.mark.parametrize("walls", [False, True])
+def test_band_edges_cover_every_row(ny, walls):
+    """Grids whose height leaves some XCD bands empty (5 rows), uneven (9,
+    43, 130 rows over 8 bands) or partly in 1-row tail tiles: every tile
+    height gives the bits of 1-row tiles, so no row is skipped or walked
+    twice at a band's edges."""
+    pr = W.random_small(11, nx=64, ny=ny, walls=walls, steps=8)
+    _, want = run_gpu(pr, "fp32", pr.steps, rows=1)
+    for rows in (2, 3, 7, 0):
+        _, got = run_gpu(pr, "fp32", pr.steps, rows=rows)
+        for k in ("phi", "psi", "ux", "uy", "P"):
+            assert np.array_equal(got[k], want[k]), (rows, k)
+
+
 def test_tile_height_does_not_change_results():
     """Each site's arithmetic is independent of the tiling: bitwise equal."""
     pr = W.random_small(3, nx=150, ny=70, steps=25)
