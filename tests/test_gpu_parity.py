@@ -349,6 +349,38 @@ def test_band_edges_cover_every_row(ny, walls):
             assert np.array_equal(got[k], want[k]), (rows, k)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16dev"])
+def test_odd_grid_equals_its_tiled_small_copy(precision):
+    """2047x2047 (odd, so one column per lane) filled with 23x23 copies of
+    an 89x89 periodic field: after a few steps the large fields are the
+    small ones tiled, bitwise for float32 storage and at the float16 bar
+    for float16 storage (its rounding bits depend on the site), and at the
+    storage's bar against the oracle's run of the small field.  The large
+    grid runs the large-grid tile plan of the one-column kernels."""
+    n, p = 2047, 89
+    steps = 3
+    pr = W.c3_many_drops(precision=precision, nx=p, ny=p, ndrops=2)
+    _, small = run_gpu(pr, precision, steps)
+    reps = (n // p, n // p)
+    sim = lbm.Simulation(dict(pr.params, nx=n, ny=n, precision=precision))
+    assert sim.step_kernel_name().split(", ")[1] == "1", sim.step_kernel_name()
+    sim.init_fields(*[np.tile(a, reps) for a in pr.fields0])
+    sim.step(steps)
+    got = sim.read_fields()
+    sim.close()
+    del sim
+    _, ref = run_oracle(pr, steps)
+    check(got, {k: np.tile(ref[k], reps) for k in ("phi", "psi", "ux", "uy")}, TOL[precision],
+          f"odd grid {precision} {n}^2 against the oracle")
+    want = {k: np.tile(small[k], reps) for k in ("phi", "psi", "ux", "uy", "P")}
+    if precision == "fp16dev":
+        err = errors(got, want, FIELDS)
+        assert max(err.values()) <= TOL[precision], err
+    else:
+        for k in want:
+            assert np.array_equal(got[k], want[k]), k
+
+
 def test_tile_height_does_not_change_results():
     """Each site's arithmetic is independent of the tiling: bitwise equal."""
     pr = W.random_small(3, nx=150, ny=70, steps=25)
